@@ -1,0 +1,225 @@
+"""Benchmark: Montgomery products over HBM-resident arrays on one MI355X.
+
+One step = for each of the four moduli {469762049, 998244353, 2013265921,
+2113929217}: mont_mul over n = 2^28 residue pairs, then the chained product
+plus sum c = (a*b + c) mod P in place (2^31 Montgomery products per step).
+Inputs are seeded, uniform in [0, P), and resident in HBM before timing.
+
+Prints one JSON line (rank 0) with the headline metric, the roofline of the
+dominant kernel (mont_mul, HBM-bound), a CPU-oracle baseline on the host
+cores, and side measurements of the other hot-path rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
+N_ELEM = 1 << 28
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n-log2", type=int, default=28, help="elements per array (default 2^28)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip side measurements of other rows")
+    ap.add_argument("--only", default="", help="profiling aid: run only 'elementwise' steps")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus %d is not supported "
+                                   "(work shards by independent index ranges or products, see design notes)"
+                          % args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1609_00999_amd import mont
+    from paper_1609_00999_amd import workloads as wl
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a ROCm GPU")
+    mont.lib()
+    dev = torch.device("cuda:0")
+    n = 1 << args.n_log2
+
+    # ---------------- inputs, resident in HBM ----------------
+    t0 = time.time()
+    host_sets, sets = [], []
+    for pi in range(len(wl.PRIMES_BW)):
+        P, a, b, c = wl.bandwidth_triple(pi, n)
+        host_sets.append((P, a, b, c))
+        prm = mont.setup(P)
+        da = torch.from_numpy(a.view(np.int32)).to(dev)
+        db = torch.from_numpy(b.view(np.int32)).to(dev)
+        dc = torch.from_numpy(c.view(np.int32)).to(dev)
+        do = torch.empty_like(da)
+        sets.append((prm, da, db, dc, do))
+    torch.cuda.synchronize()
+    log("inputs resident (%.1f s)" % (time.time() - t0))
+
+    stream = torch.cuda.current_stream()
+    mul_events = []
+
+    def step(record):
+        for prm, da, db, dc, do in sets:
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            mont.mul(prm, da, db, out=do)
+            if record:
+                e1.record(stream)
+                mul_events.append((e0, e1))
+            mont.muladd(prm, da, db, dc, out=dc)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    modmul_per_step = 2 * n * len(sets)
+    value = modmul_per_step / (elapsed / args.steps) / 1e9
+    mul_ms = [a.elapsed_time(b) for a, b in mul_events]
+    mul_avg_s = sum(mul_ms) / len(mul_ms) / 1e3
+    mul_bytes = 12.0 * n                      # 2 reads + 1 write of uint32
+    achieved = mul_bytes / mul_avg_s / 1e9
+    log("step %.3f ms, %.1f Gmodmul/s; mont_mul avg %.3f ms = %.0f GB/s" % (ms_per_step, value,
+                                                                            mul_avg_s * 1e3, achieved))
+
+    # correctness spot check of the timed arrays (first and last elements)
+    import oracle
+    P, a, b, c = host_sets[0]
+    out0 = sets[0][4][:4096].cpu().numpy().view(np.uint32)
+    assert np.array_equal(out0, oracle.mont_mul(P, a[:4096], b[:4096])), "mont_mul mismatch in bench"
+
+    result = {
+        "metric": "Gmodmul/s (mont_mul + chained mul-add, n=2^28 x 4 primes) and % HBM roofline",
+        "value": round(value, 2),
+        "unit": "Gmodmul/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded uniform residues in [0,P))",
+        "config": {"workload": "bandwidth-scale elementwise Montgomery mul and chained mul-add",
+                   "n_per_prime": n, "primes": list(wl.PRIMES_BW), "ops_per_step": ["mont_mul", "mont_muladd"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": "mont_mul", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": mul_bytes,
+                     "avg_launch_ms": round(mul_avg_s * 1e3, 4)},
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(host_sets)
+
+    if not args.no_extras:
+        result["extras"] = extras(torch, mont, wl, dev)
+
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(host_sets):
+    """The oracle on the host cores over the same step (all four moduli,
+    mul and mul-add over the full arrays), split over all host threads."""
+    import oracle
+    threads = oracle.default_threads()
+    total = 0
+    t0 = time.perf_counter()
+    for P, a, b, c in host_sets:
+        oracle.mont_mul(P, a, b, threads=threads)
+        oracle.mont_muladd(P, a, b, c, threads=threads)
+        total += 2 * a.size
+    dt = time.perf_counter() - t0
+    log("cpu baseline %.1f s" % dt)
+    return {"value": round(total / dt / 1e9, 4), "unit": "Gmodmul/s", "cores": threads, "kind": "oracle",
+            "sample": "one full step: mont_mul and mont_muladd over 2^28 elements for each of the 4 primes",
+            "seconds": round(dt, 2), "cpu_model": cpu_model()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def timed(torch, fn, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def extras(torch, mont, wl, dev):
+    """Side measurements: the n = 2^20 to/mul/from pipeline and mont_pow."""
+    out = {}
+    P = wl.P_PLAIN
+    prm = mont.setup(P)
+    a, b = wl.plain_pairs()
+    da = torch.from_numpy(a.view(np.int32)).to(dev)
+    db = torch.from_numpy(b.view(np.int32)).to(dev)
+    ta, tb, tc = torch.empty_like(da), torch.empty_like(da), torch.empty_like(da)
+
+    def pipe():
+        mont.to_mont(prm, da, out=ta)
+        mont.to_mont(prm, db, out=tb)
+        mont.mul(prm, ta, tb, out=tc)
+        mont.from_mont(prm, tc, out=tc)
+    s = timed(torch, pipe, 50)
+    out["plain_pipeline_n2^20"] = {"us": round(s * 1e6, 2), "Gmodmul_per_s": round(a.size / s / 1e9, 2)}
+
+    P = wl.P_POW
+    prm = mont.setup(P)
+    base, e = wl.pow_inputs()
+    dbase = torch.from_numpy(base.view(np.int32)).to(dev)
+    dexp = torch.from_numpy(e.view(np.int32)).to(dev)
+    dout = torch.empty_like(dbase)
+    s = timed(torch, lambda: mont.pow(prm, dbase, dexp, out=dout), 10)
+    # algorithmic count: 31 squarings + popcount(e) products per element
+    pc = int(np.unpackbits(e.view(np.uint8)).sum())
+    alg = 31 * e.size + pc
+    executed = 47 * e.size
+    out["pow_n2^24"] = {"ms": round(s * 1e3, 4), "pow_per_s": round(e.size / s, 1),
+                        "Gmodmul_per_s_algorithmic": round(alg / s / 1e9, 2),
+                        "Gredc_per_s_executed": round(executed / s / 1e9, 2)}
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,132 @@
+/*
+ * mont.h -- C ABI of libmont: Montgomery modular arithmetic on 32-bit
+ * residues for AMD Instinct MI355X (gfx950).
+ *
+ * The arithmetic is Montgomery's reduction as stated in Meng, "Automatic
+ * Generation of Vectorized Montgomery Algorithm" (arXiv:1609.00999), section
+ * 3.1 and Algorithm 2, with R = 2^32:
+ *   - precomputation: P' with R*R^-1 - P*P' = 1, i.e. P' = -P^-1 mod 2^32;
+ *   - residue representation: x_bar = x*R mod P;
+ *   - REDC(a_bar, b_bar): T = a_bar*b_bar, m = (T mod R)*P' mod R,
+ *     t = (T + m*P)/R, then one conditional subtraction of P.  The result is
+ *     a_bar*b_bar*R^-1 mod P, canonical in [0, P), provided a_bar*b_bar < R*P.
+ *
+ * Conventions for every entry point below:
+ *   - Pointers named d_* are DEVICE pointers (memory on the current HIP
+ *     device); every other pointer is a HOST pointer.  The caller owns all of
+ *     them.  Element arrays are contiguous uint32.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every device operation is asynchronous on that stream: results are valid
+ *     once the stream has been synchronized.  Host-side validation happens
+ *     before anything is enqueued; on error nothing is enqueued.
+ *   - In-place operation (d_out equal to an input pointer) is allowed for the
+ *     elementwise calls.  Partially overlapping arrays are not.
+ *   - n == 0 is valid and enqueues nothing.  A NULL device pointer with
+ *     n > 0 returns MONT_EINVAL.
+ *   - No function throws; each returns a mont_status.  HIP runtime failures
+ *     (launch errors) are reported as MONT_EHIP.
+ *   - Operands outside [0, P) for mont_mul, mont_muladd and mont_pow give a
+ *     deterministic but unspecified value (Algorithm 2 needs a_bar*b_bar < RP).
+ */
+#ifndef MONT_H
+#define MONT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define MONT_API __attribute__((visibility("default")))
+#else
+#define MONT_API
+#endif
+
+typedef int mont_status;
+#define MONT_OK 0
+#define MONT_EINVAL (-1)   /* bad argument: modulus, size, pointer, id      */
+#define MONT_ERANGE (-2)   /* a size or index exceeds what the call supports */
+#define MONT_ENOROOT (-3)  /* 2^k does not divide P-1 for the needed length  */
+#define MONT_ENOMEM (-4)   /* scratch or device memory too small / exhausted */
+#define MONT_EHIP (-5)     /* HIP runtime error                              */
+#define MONT_ETIMEOUT (-6) /* a bounded device-side wait gave up             */
+
+/*
+ * Per-modulus constants (section 3.1, Montgomery precomputation).  Plain
+ * data: the caller owns it and may copy it freely.
+ */
+typedef struct mont_params {
+  uint32_t P;      /* odd modulus, 3 <= P < 2^31                          */
+  uint32_t Pprime; /* P' = -P^-1 mod 2^32, so that R*R^-1 - P*P' = 1     */
+  uint32_t R1;     /* R mod P, the residue of 1                           */
+  uint32_t R2;     /* R^2 mod P; REDC(x*R2) is the residue of x           */
+  uint32_t k;      /* largest k with 2^k dividing P-1                     */
+} mont_params;
+
+/* Human-readable text for a status code (static storage, never NULL). */
+MONT_API const char* mont_strerror(mont_status status);
+
+/*
+ * mont_setup -- section 3.1 precomputation for modulus P with R = 2^32.
+ * Fills *out.  Returns MONT_EINVAL if out is NULL, P is even, P < 3 or
+ * P >= 2^31 (t < 2P must fit in 32 bits).  Odd composite P is accepted:
+ * REDC needs only gcd(P, R) = 1.  Host only; enqueues nothing.
+ */
+MONT_API mont_status mont_setup(uint32_t P, mont_params* out);
+
+/*
+ * mont_to -- residues: d_out[i] = d_in[i]*R mod P, computed as
+ * REDC(d_in[i], R2).  Accepts every uint32 input (d_in[i]*R2 < R*P holds for
+ * any 32-bit d_in[i]).  prm is a host pointer to constants from mont_setup.
+ */
+MONT_API mont_status mont_to(const mont_params* prm, const uint32_t* d_in, uint32_t* d_out, size_t n, void* stream);
+
+/*
+ * mont_from -- back from residues: d_out[i] = d_in[i]*R^-1 mod P, computed as
+ * REDC(d_in[i], 1).  Accepts every uint32 input; output in [0, P).
+ */
+MONT_API mont_status mont_from(const mont_params* prm, const uint32_t* d_in, uint32_t* d_out, size_t n, void* stream);
+
+/*
+ * mont_mul -- Algorithm 2 elementwise: d_out[i] = REDC(d_a[i], d_b[i]) =
+ * d_a[i]*d_b[i]*R^-1 mod P.  Operands are residues in [0, P).
+ */
+MONT_API mont_status mont_mul(const mont_params* prm, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out,
+                     size_t n, void* stream);
+
+/*
+ * mont_muladd -- d_out[i] = (REDC(d_a[i], d_b[i]) + d_c[i]) mod P: a Montgomery
+ * product followed by an ordinary modular addition, which the residue
+ * representation leaves unchanged (section 3.1).  Operands in [0, P).
+ * d_out may equal d_c (accumulate in place).
+ */
+MONT_API mont_status mont_muladd(const mont_params* prm, const uint32_t* d_a, const uint32_t* d_b, const uint32_t* d_c,
+                        uint32_t* d_out, size_t n, void* stream);
+
+/*
+ * mont_pow -- d_out[i] = d_base[i]^d_exp[i] in the residue system: d_base[i]
+ * is a residue in [0, P), d_exp[i] an ordinary 32-bit exponent, and the result
+ * is the residue of a^e (0^0 gives the residue of 1).  Every step is a REDC
+ * product of residues, which keeps long chains of products in residue form
+ * as section 3.1 recommends.
+ */
+MONT_API mont_status mont_pow(const mont_params* prm, const uint32_t* d_base, const uint32_t* d_exp, uint32_t* d_out,
+                     size_t n, void* stream);
+
+/*
+ * Launch-shape tuning of the streaming elementwise kernels (used by the
+ * autotuner).  op: 0 = to, 1 = from, 2 = mul, 3 = muladd, 4 = pow.  block is
+ * 256 or 512 threads, vpt 1, 2 or 4 128-bit vectors per thread, nontemporal
+ * 0 or 1.  Settings are process-wide and take effect on the next call; they
+ * never change results.  Returns MONT_EINVAL for values outside those sets.
+ */
+MONT_API mont_status mont_elem_tune_set(int op, int block, int vpt, int nontemporal);
+MONT_API mont_status mont_elem_tune_get(int op, int* block, int* vpt, int* nontemporal);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MONT_H */

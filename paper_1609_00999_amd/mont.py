@@ -1,0 +1,190 @@
+"""Python binding of libmont (argument marshalling only).
+
+Every function takes ROCm device tensors (torch.uint32, or torch.int32 read
+as uint32 bit patterns), checks shapes on the host and calls the C ABI on
+torch's current HIP stream.  All arithmetic happens in libmont's HIP kernels;
+there is no host fallback: if libmont.so is missing the call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmont.so")
+
+c_u32 = ctypes.c_uint32
+c_size = ctypes.c_size_t
+c_vp = ctypes.c_void_p
+
+
+class MontParams(ctypes.Structure):
+    """Mirror of ``mont_params`` (include/mont.h)."""
+    _fields_ = [("P", c_u32), ("Pprime", c_u32), ("R1", c_u32), ("R2", c_u32), ("k", c_u32)]
+
+    def __repr__(self):
+        return "MontParams(P=%d, Pprime=%d, R1=%d, R2=%d, k=%d)" % (self.P, self.Pprime, self.R1, self.R2,
+                                                                    self.k)
+
+
+class MontError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what or "libmont", strerror(status), status))
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmont.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmont.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    pp = ctypes.POINTER(MontParams)
+    L.mont_strerror.argtypes = [ctypes.c_int]
+    L.mont_strerror.restype = ctypes.c_char_p
+    L.mont_setup.argtypes = [c_u32, pp]
+    for name in ("mont_to", "mont_from"):
+        getattr(L, name).argtypes = [pp, c_vp, c_vp, c_size, c_vp]
+    for name in ("mont_mul", "mont_pow"):
+        getattr(L, name).argtypes = [pp, c_vp, c_vp, c_vp, c_size, c_vp]
+    L.mont_muladd.argtypes = [pp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]
+    L.mont_elem_tune_set.argtypes = [ctypes.c_int] * 4
+    L.mont_elem_tune_get.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
+    _register_ntt(L)
+    _lib = L
+    return L
+
+
+def _register_ntt(L):
+    """Argument types of the transform entry points (filled in by ntt.py)."""
+    from . import ntt as _ntt
+    _ntt.register(L)
+
+
+def strerror(status: int) -> str:
+    try:
+        return lib().mont_strerror(status).decode()
+    except RuntimeError:
+        return "status %d" % status
+
+
+def check(status: int, what: str = "") -> None:
+    if status != 0:
+        raise MontError(status, what)
+
+
+def setup(P: int) -> MontParams:
+    """Section 3.1 precomputation for modulus P (R = 2^32)."""
+    out = MontParams()
+    check(lib().mont_setup(P, ctypes.byref(out)), "mont_setup(%d)" % P)
+    return out
+
+
+# --------------------------------------------------------------------------
+# tensor helpers
+# --------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def dev_ptr(t, name: str = "tensor") -> int:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a ROCm device tensor" % name)
+    if t.dtype not in (torch.uint32, torch.int32):
+        raise TypeError("%s must be uint32 or int32, got %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def empty_like_u32(t):
+    torch = _torch()
+    return torch.empty(t.shape, dtype=t.dtype, device=t.device)
+
+
+def _unary(fn, prm, x, out, name):
+    if out is None:
+        out = empty_like_u32(x)
+    if out.numel() != x.numel():
+        raise ValueError("out has %d elements, input %d" % (out.numel(), x.numel()))
+    check(fn(ctypes.byref(prm), dev_ptr(x, "x"), dev_ptr(out, "out"), x.numel(), stream_handle()), name)
+    return out
+
+
+def to_mont(prm: MontParams, x, out=None):
+    """Residues x*R mod P (any uint32 input)."""
+    return _unary(lib().mont_to, prm, x, out, "mont_to")
+
+
+def from_mont(prm: MontParams, x, out=None):
+    """x*R^-1 mod P (any uint32 input)."""
+    return _unary(lib().mont_from, prm, x, out, "mont_from")
+
+
+def mul(prm: MontParams, a, b, out=None):
+    """REDC(a*b) elementwise (Algorithm 2); operands are residues in [0, P)."""
+    if a.numel() != b.numel():
+        raise ValueError("operand sizes differ")
+    if out is None:
+        out = empty_like_u32(a)
+    if out.numel() != a.numel():
+        raise ValueError("out size differs")
+    check(lib().mont_mul(ctypes.byref(prm), dev_ptr(a, "a"), dev_ptr(b, "b"), dev_ptr(out, "out"), a.numel(),
+                         stream_handle()), "mont_mul")
+    return out
+
+
+def muladd(prm: MontParams, a, b, c, out=None):
+    """(REDC(a*b) + c) mod P elementwise; out may be c (in place)."""
+    if not (a.numel() == b.numel() == c.numel()):
+        raise ValueError("operand sizes differ")
+    if out is None:
+        out = empty_like_u32(a)
+    if out.numel() != a.numel():
+        raise ValueError("out size differs")
+    check(lib().mont_muladd(ctypes.byref(prm), dev_ptr(a, "a"), dev_ptr(b, "b"), dev_ptr(c, "c"),
+                            dev_ptr(out, "out"), a.numel(), stream_handle()), "mont_muladd")
+    return out
+
+
+def pow(prm: MontParams, base, exp, out=None):  # noqa: A001 - mirrors mont_pow
+    """Residue of a^e for residues ``base`` and ordinary uint32 exponents."""
+    if base.numel() != exp.numel():
+        raise ValueError("operand sizes differ")
+    if out is None:
+        out = empty_like_u32(base)
+    if out.numel() != base.numel():
+        raise ValueError("out size differs")
+    check(lib().mont_pow(ctypes.byref(prm), dev_ptr(base, "base"), dev_ptr(exp, "exp"), dev_ptr(out, "out"),
+                         base.numel(), stream_handle()), "mont_pow")
+    return out
+
+
+ELEM_OPS = {"to": 0, "from": 1, "mul": 2, "muladd": 3, "pow": 4}
+
+
+def elem_tune_set(op: str, block: int, vpt: int, nontemporal: bool) -> None:
+    check(lib().mont_elem_tune_set(ELEM_OPS[op], block, vpt, int(bool(nontemporal))), "mont_elem_tune_set")
+
+
+def elem_tune_get(op: str):
+    b, v, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib().mont_elem_tune_get(ELEM_OPS[op], ctypes.byref(b), ctypes.byref(v), ctypes.byref(n)),
+          "mont_elem_tune_get")
+    return b.value, v.value, bool(n.value)

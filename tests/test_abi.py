@@ -1,0 +1,96 @@
+"""The C ABI without a GPU: every declared symbol is exported, and host-side
+validation rejects bad arguments before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER_DIR = os.path.join(ROOT, "include")
+
+
+def declared_symbols():
+    names = []
+    for fn in sorted(os.listdir(HEADER_DIR)):
+        if fn.endswith(".h"):
+            text = open(os.path.join(HEADER_DIR, fn)).read()
+            names += re.findall(r"MONT_API\s+[\w\s\*]+?\b(\w+)\s*\(", text)
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1609_00999_amd import mont
+    return mont.lib()
+
+
+def test_header_declares_entry_points():
+    names = declared_symbols()
+    for must in ("mont_setup", "mont_to", "mont_from", "mont_mul", "mont_muladd", "mont_pow", "mont_strerror"):
+        assert must in names
+
+
+@pytest.mark.parametrize("name", declared_symbols())
+def test_symbol_exported(L, name):
+    assert hasattr(L, name), name
+
+
+def test_no_stray_exports():
+    import subprocess
+    from paper_1609_00999_amd import mont
+    out = subprocess.run(["nm", "-D", "--defined-only", mont.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert exported <= set(declared_symbols()), exported - set(declared_symbols())
+
+
+def test_setup_host_only(L):
+    from paper_1609_00999_amd import mont
+    import oracle
+    for P in (3, 15, 17, 469762049, 998244353, 2013265921, 2113929217, 2147483647):
+        prm, ref = mont.setup(P), oracle.setup(P)
+        assert (prm.Pprime, prm.R1, prm.R2, prm.k) == (ref.Pprime, ref.R1, ref.R2, ref.k)
+    for bad in (0, 1, 2, 4, 100, 1 << 31, (1 << 32) - 1):
+        with pytest.raises(mont.MontError) as ei:
+            mont.setup(bad)
+        assert ei.value.status == -1
+    assert L.mont_setup(17, None) == -1
+
+
+def test_validation_without_gpu(L):
+    from paper_1609_00999_amd import mont
+    prm = mont.setup(2013265921)
+    p = ctypes.byref(prm)
+    # n == 0 is a no-op even with NULL pointers
+    assert L.mont_mul(p, None, None, None, 0, None) == 0
+    assert L.mont_to(p, None, None, 0, None) == 0
+    # NULL device pointers with n > 0
+    assert L.mont_mul(p, None, None, None, 5, None) == -1
+    assert L.mont_muladd(p, 16, 16, None, 16, 5, None) == -1
+    assert L.mont_pow(p, 16, None, 16, 5, None) == -1
+    assert L.mont_from(p, None, 16, 5, None) == -1
+    # a parameter block that mont_setup did not produce
+    bad = mont.MontParams(P=2013265921, Pprime=1, R1=0, R2=0, k=0)
+    assert L.mont_mul(ctypes.byref(bad), 16, 16, 16, 5, None) == -1
+    even = mont.MontParams(P=10, Pprime=0, R1=0, R2=0, k=0)
+    assert L.mont_to(ctypes.byref(even), 16, 16, 5, None) == -1
+    assert L.mont_mul(None, 16, 16, 16, 5, None) == -1
+
+
+def test_strerror(L):
+    from paper_1609_00999_amd import mont
+    for s in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert isinstance(mont.strerror(s), str) and mont.strerror(s)
+
+
+def test_elem_tune(L):
+    from paper_1609_00999_amd import mont
+    old = mont.elem_tune_get("mul")
+    try:
+        mont.elem_tune_set("mul", 512, 2, False)
+        assert mont.elem_tune_get("mul") == (512, 2, False)
+        with pytest.raises(mont.MontError):
+            mont.elem_tune_set("mul", 128, 2, False)
+        assert L.mont_elem_tune_set(9, 256, 1, 1) == -1
+    finally:
+        mont.elem_tune_set("mul", *old)
