@@ -25,6 +25,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published
 N_ELEM = 1 << 28
 
+# HBM bytes per mont_mul launch at n = 2^28 from two rocprofv3 --pmc runs
+# (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain
+# 1 GiB copy kernel gives), valid only for the kernel source they were taken on.
+MUL_TRAFFIC = {"src_hash": "d28e69684c7d95fd", "n": 1 << 28, "bytes": 3145811 * 1024,
+               "profile": "profiles/elementwise_mul_muladd_n2e28_x4primes.md"}
+
+
+def elementwise_src_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_1609_00999_amd/csrc/elementwise.hip", "paper_1609_00999_amd/csrc/modarith.hpp"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -34,7 +49,9 @@ def parse():
     ap.add_argument("--n-log2", type=int, default=28, help="elements per array (default 2^28)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip side measurements of other rows")
-    ap.add_argument("--only", default="", help="profiling aid: run only 'elementwise' steps")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 2^28-element int32 copy kernel (bitwise_not) three times, "
+                         "whose HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
     return ap.parse_args()
 
 
@@ -113,6 +130,10 @@ def main():
     out0 = sets[0][4][:4096].cpu().numpy().view(np.uint32)
     assert np.array_equal(out0, oracle.mont_mul(P, a[:4096], b[:4096])), "mont_mul mismatch in bench"
 
+    traffic = None
+    if n == MUL_TRAFFIC["n"] and elementwise_src_hash() == MUL_TRAFFIC["src_hash"]:
+        traffic = MUL_TRAFFIC["bytes"]
+
     result = {
         "metric": "Gmodmul/s (mont_mul + chained mul-add, n=2^28 x 4 primes) and % HBM roofline",
         "value": round(value, 2),
@@ -131,9 +152,18 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": "mont_mul", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "algorithmic_bytes_per_launch": mul_bytes,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": mul_bytes,
                      "avg_launch_ms": round(mul_avg_s * 1e3, 4)},
     }
+
+    if args.copy_calibration:
+        x = sets[0][1]
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.bitwise_not(x, out=y)
+        torch.cuda.synchronize()
+        result["copy_calibration"] = {"kernel": "torch bitwise_not (int32)", "read_bytes": 4 * n,
+                                      "write_bytes": 4 * n}
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(host_sets)
@@ -150,15 +180,21 @@ def cpu_baseline(host_sets):
     import oracle
     threads = oracle.default_threads()
     total = 0
+    reps = 0
     t0 = time.perf_counter()
-    for P, a, b, c in host_sets:
-        oracle.mont_mul(P, a, b, threads=threads)
-        oracle.mont_muladd(P, a, b, c, threads=threads)
-        total += 2 * a.size
+    while True:
+        for P, a, b, c in host_sets:
+            oracle.mont_mul(P, a, b, threads=threads)
+            oracle.mont_muladd(P, a, b, c, threads=threads)
+            total += 2 * a.size
+        reps += 1
+        if time.perf_counter() - t0 >= 10.0 or reps >= 50:
+            break
     dt = time.perf_counter() - t0
-    log("cpu baseline %.1f s" % dt)
+    log("cpu baseline %.1f s over %d steps" % (dt, reps))
     return {"value": round(total / dt / 1e9, 4), "unit": "Gmodmul/s", "cores": threads, "kind": "oracle",
-            "sample": "one full step: mont_mul and mont_muladd over 2^28 elements for each of the 4 primes",
+            "sample": "%d full steps (mont_mul and mont_muladd over 2^28 elements for each of the 4 primes), "
+                      "repeated until at least 10 s of host time" % reps,
             "seconds": round(dt, 2), "cpu_model": cpu_model()}
 
 
