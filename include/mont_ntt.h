@@ -1,0 +1,149 @@
+/*
+ * mont_ntt.h -- C ABI of libmont's number-theoretic transforms and
+ * polynomial products modulo word-size Fourier primes (AMD MI355X, gfx950).
+ *
+ * Every butterfly multiplies an ordinary residue by a twiddle factor kept in
+ * Montgomery form and reduces with REDC (Meng, arXiv:1609.00999, section 3.1,
+ * Algorithm 2, R = 2^32), so REDC(x * w R) = x w mod P.  Primes P = c 2^k + 1
+ * (Fourier primes, section 3.1) have roots of unity of order 2^n for n <= k.
+ * The paper uses this arithmetic inside modular FFT and polynomial-product
+ * libraries (sections 1 and 5); the transforms themselves are the textbook
+ * radix-2 ones:
+ *   forward:  X_j = sum_i x_i w^(i * rev(j)), natural order in, bit-reversed
+ *             order out (decimation in frequency);
+ *   inverse:  x_i = N^-1 sum_j X_j w^(-i * rev(j)), bit-reversed in, natural
+ *             out (decimation in time);
+ * with w = g^((P-1)/N) and g the smallest primitive root modulo P.
+ *
+ * Conventions are those of mont.h: d_* are device pointers owned by the
+ * caller, stream is a hipStream_t (NULL = null stream), calls are
+ * asynchronous on it, validation happens before anything is enqueued, and
+ * coefficients are ordinary residues in [0, P) (not Montgomery form).
+ */
+#ifndef MONT_NTT_H
+#define MONT_NTT_H
+
+#include "mont.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque context: per-prime constants and resident twiddle tables. */
+typedef struct ntt_ctx ntt_ctx;
+
+/*
+ * ntt_ctx_create -- per prime: section 3.1 constants, the smallest primitive
+ * root g, and device-resident twiddle tables (forward and inverse, 2^L words
+ * each with L = min(log2_nmax, v2(P-1))), generated on the device by REDC
+ * products of repeated squares.  Allocates device memory (8 * 2^L bytes per
+ * prime) and synchronizes the device.  primes: host array of nprimes
+ * (1..64) odd primes < 2^31.  log2_nmax in [1, 27].  The context is
+ * read-only afterwards and may be shared by streams and threads.
+ * Errors: MONT_EINVAL (bad prime or argument), MONT_ENOMEM, MONT_EHIP.
+ */
+MONT_API mont_status ntt_ctx_create(const uint32_t* primes, int nprimes, int log2_nmax, ntt_ctx** out);
+
+/* Frees the context's device memory (synchronizes the device first). */
+MONT_API mont_status ntt_ctx_destroy(ntt_ctx* ctx);
+
+/*
+ * ntt_ctx_prime -- introspection for prime prime_id: its parameters, the root
+ * w of order 2^log2_max used by the tables (ordinary residue), log2_max, and
+ * device pointers to the tables (entry h + i, h = 2^s, i < h, holds the
+ * Montgomery form of w_{2h}^i, respectively w_{2h}^-i, with w_{2h} =
+ * w^(2^log2_max / 2h); entry 0 is unused).  Any output pointer may be NULL.
+ */
+MONT_API mont_status ntt_ctx_prime(const ntt_ctx* ctx, int prime_id, mont_params* prm, uint32_t* root,
+                                   uint32_t* log2_max, const uint32_t** d_twf, const uint32_t** d_twi);
+
+/* ntt_ctx_read_twiddles -- synchronous copy of prime prime_id's forward and
+ * inverse tables (2^log2_max words each) into HOST arrays h_fwd and h_inv. */
+MONT_API mont_status ntt_ctx_read_twiddles(const ntt_ctx* ctx, int prime_id, uint32_t* h_fwd, uint32_t* h_inv);
+
+/*
+ * ntt_forward / ntt_inverse -- in-place transform of d_x[0 .. 2^log2n) with the
+ * root of order 2^log2n (see above for orders).  ntt_inverse includes the
+ * factor N^-1, so ntt_inverse(ntt_forward(x)) = x.  Values must be in [0, P).
+ * Errors: MONT_EINVAL, MONT_ENOROOT (log2n above the prime's table).
+ */
+MONT_API mont_status ntt_forward(const ntt_ctx* ctx, int prime_id, uint32_t* d_x, uint32_t log2n, void* stream);
+MONT_API mont_status ntt_inverse(const ntt_ctx* ctx, int prime_id, uint32_t* d_x, uint32_t log2n, void* stream);
+
+/*
+ * ntt_polymul -- product of two polynomials modulo prime prime_id, with plain
+ * kernel launches (one for lengths up to 2^13, three above):
+ *   d_out[k] = sum_{i+j=k} d_a[i] d_b[j] mod P,  k = 0 .. da+db,
+ * for d_a of da+1 and d_b of db+1 coefficients in [0, P).  The transform
+ * length is N = 2^n, the least power of two >= da+db+1.  d_scratch must hold
+ * ntt_polymul_scratch_bytes(da, db) bytes (0 when N <= 2^13, else 8N);
+ * d_out must not overlap the inputs.  Errors: MONT_EINVAL, MONT_ERANGE
+ * (da+db+1 > 2^31), MONT_ENOROOT (N above the prime's table), MONT_ENOMEM
+ * (scratch too small).
+ */
+MONT_API size_t ntt_polymul_scratch_bytes(uint32_t da, uint32_t db);
+MONT_API mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint32_t* d_a, uint32_t da,
+                                 const uint32_t* d_b, uint32_t db, uint32_t* d_out, void* d_scratch,
+                                 size_t scratch_bytes, void* stream);
+
+/* One product of a batch: operands at d_in + a_off (da+1 words) and
+ * d_in + b_off (db+1 words), result at d_out + c_off (da+db+1 words). */
+typedef struct polymul_desc {
+  uint32_t prime_id;
+  uint32_t da, db;
+  uint32_t reserved; /* must be 0 */
+  uint64_t a_off, b_off, c_off;
+} polymul_desc;
+
+/* Opaque batch plan: the product descriptors and the ordered task list,
+ * resident on the device. */
+typedef struct ntt_plan ntt_plan;
+
+/*
+ * ntt_plan_create -- plans a batch of `count` products of uneven lengths,
+ * each with its own prime, for ONE persistent launch.  Products with N <=
+ * 2^13 are single tasks; longer ones are split into column tiles of both
+ * operands, row blocks (forward rows, pointwise product, inverse rows) and
+ * inverse column tiles, with per-product completion counters.  Tasks are
+ * ordered so that every prerequisite precedes its dependants: forward column
+ * tiles, half the single tasks, row blocks, the other half, inverse column
+ * tiles, each group longest-first, or shuffled within groups when
+ * order_seed != 0 (for determinism tests).  descs is a host array; it is
+ * copied.  Allocates device memory for the plan (not for the data).
+ * Errors: MONT_EINVAL, MONT_ERANGE, MONT_ENOROOT, MONT_ENOMEM, MONT_EHIP.
+ */
+MONT_API mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
+                                     ntt_plan** out);
+
+/* Sizes a caller needs: scratch bytes, task count, the minimum lengths (in
+ * words) of d_in and d_out, and the default persistent grid (resident
+ * workgroups on the device).  Any output pointer may be NULL. */
+MONT_API mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, uint32_t* ntasks,
+                                   uint64_t* in_words, uint64_t* out_words, int* default_grid);
+
+/*
+ * ntt_plan_execute -- zeroes the scratch header with a fill kernel, then runs
+ * the whole batch in one persistent launch of `grid` workgroups (0 = the
+ * default) that take tasks from a device counter.  Waits on another task's
+ * completion spin at most spin_limit sleeps (0 = 2^24); on expiry the launch
+ * records a timeout, skips the dependent tasks and drains.  d_scratch must
+ * hold the plan's scratch bytes; d_in and d_out the plan's word counts.  The
+ * result is identical for every grid size and task order.  Enqueues two
+ * kernels and no memset or allocation, so the call may be captured in a HIP
+ * graph.  Calls that share a scratch buffer must not overlap.
+ */
+MONT_API mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_in, uint32_t* d_out, void* d_scratch,
+                                      size_t scratch_bytes, int grid, uint32_t spin_limit, void* stream);
+
+/* Synchronizes `stream` and reports whether the last execution on d_scratch
+ * completed (MONT_OK) or timed out in a dependency wait (MONT_ETIMEOUT). */
+MONT_API mont_status ntt_plan_status(const ntt_plan* plan, const void* d_scratch, void* stream);
+
+/* Frees the plan's device memory (synchronizes the device first). */
+MONT_API mont_status ntt_plan_destroy(ntt_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MONT_NTT_H */

@@ -1,0 +1,889 @@
+// ntt.hip -- radix-2 number-theoretic transforms and polynomial products
+// modulo word-size Fourier primes, with Montgomery-form twiddles.
+//
+// The butterflies apply REDC (arXiv:1609.00999, section 3.1, Algorithm 2) to
+// an ordinary residue times a twiddle kept in Montgomery form, w_bar = w R mod
+// P, so REDC(x * w_bar) = x w mod P and the data never leave the ordinary
+// representation.  P = c 2^k + 1 (a Fourier prime) has roots of unity of
+// every order 2^n <= 2^k, which the transforms need.
+//
+// Transform layout (no permutation pass anywhere):
+//   forward  = decimation in frequency (Gentleman-Sande), natural order in,
+//              bit-reversed order out: stages h = N/2, ..., 1 with
+//              (x, y) -> (x + y, (x - y) w_{2h}^i);
+//   inverse  = decimation in time (Cooley-Tukey), bit-reversed in, natural
+//              out: stages h = 1, ..., N/2 with
+//              (x, y) -> (x + y w_{2h}^-i, x - y w_{2h}^-i).
+// Twiddle tables hold w_{2h}^i at index h + i (h = 2^s, 0 <= i < h), so any
+// stage of any length N <= Nmax reads a contiguous run.
+//
+// Lengths up to 2^13 are done by one workgroup in LDS.  Longer transforms
+// (N = 2^n, n = n1 + 13) take two passes over HBM: a column pass over tiles
+// of 2^n1 rows x C adjacent columns (the first n1 stages, rows strided by
+// 2^13 in memory) and a row pass over contiguous blocks of 2^13 (the last 13
+// stages).  A polynomial product fuses the forward row pass of both operands,
+// the pointwise product and the first 13 inverse stages into one row task.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <random>
+#include <vector>
+
+#include "internal.hpp"
+#include "modarith.hpp"
+#include "mont_ntt.h"
+
+namespace mont {
+
+constexpr int kRowLog = 13;            // row block = small-product limit: 2^13 residues
+constexpr int kLdsWords = 1 << 14;     // 64 KiB of LDS per workgroup
+constexpr int kMaxLog = 27;
+
+// Per-prime device constants.
+struct PrimeDev {
+  uint32_t P, Pp, R1, R2;
+  uint32_t logmax;          // tables cover lengths up to 2^logmax
+  uint32_t pad[3];
+  const uint32_t* twf;      // twf[h + i] = residue of w_{2h}^i
+  const uint32_t* twi;      // twi[h + i] = residue of w_{2h}^-i
+  uint32_t s1[32];          // s1[n] = R N^-1 mod P  (REDC(x s1) = x / N)
+  uint32_t s2[32];          // s2[n] = R^2 N^-1 mod P (REDC(x s2) = x R / N)
+};
+
+// One product in a batch plan.
+struct ProdDev {
+  uint32_t prime_id, n, da, db;
+  uint64_t a_off, b_off, c_off, scr_off;
+  uint32_t lc;              // log2 of the columns per column tile
+  uint32_t ntiles;          // column tiles per operand
+  uint32_t nblocks;         // row blocks (2^(n - 13))
+  uint32_t pad;
+};
+
+enum TaskKind : uint32_t { T_SMALL = 0, T_COLF_A = 1, T_COLF_B = 2, T_ROW = 3, T_COLI = 4 };
+
+// Scratch header used by the persistent kernel (words).
+constexpr int kHdrWords = 64;          // [0] queue head, [1] status
+constexpr uint32_t kStatusTimeout = 1;
+
+namespace {
+
+__device__ __forceinline__ Mod mod_of(const PrimeDev& pr) { return Mod{pr.P, pr.Pp}; }
+
+// ---------------------------------------------------------------------------
+// LDS stages.  X is viewed as rows x C columns (C = 2^lc, element (k, c) at
+// X[k*C + c]); the transform runs along rows, independently per column.  The
+// global index of element (k, c) is colbase + c + k*S with S = 2^rs, so the
+// stage with row half-distance h' = 2^s has global half-size h = h' S and
+// twiddle index h + (i mod h) = (h' << rs) + colbase + c + ((k mod h') << rs).
+// NA arrays at X and X + off are transformed together (one barrier per stage).
+// ---------------------------------------------------------------------------
+
+template <int NT, int NA>
+__device__ void lds_dif(uint32_t* X, int off, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw,
+                        Mod md) {
+  const int nb = 1 << (lr - 1 + lc);
+  const uint32_t cmask = (1u << lc) - 1;
+  for (int s = lr - 1; s >= 0; s--) {
+    const uint32_t hmask = (1u << s) - 1;
+    for (int b = threadIdx.x; b < nb; b += NT) {
+      const uint32_t c = b & cmask;
+      const uint32_t q = (uint32_t)b >> lc;
+      const uint32_t k = ((q >> s) << (s + 1)) | (q & hmask);
+      const uint32_t i1 = (k << lc) | c;
+      const uint32_t i2 = i1 + (1u << (s + lc));
+      const uint32_t w = tw[(1u << (s + rs)) + colbase + c + ((q & hmask) << rs)];
+#pragma unroll
+      for (int a = 0; a < NA; a++) {
+        uint32_t* Y = X + a * off;
+        const uint32_t u = Y[i1], v = Y[i2];
+        Y[i1] = madd(u, v, md.P);
+        Y[i2] = mmul(msub(u, v, md.P), w, md);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__device__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw, Mod md) {
+  const int nb = 1 << (lr - 1 + lc);
+  const uint32_t cmask = (1u << lc) - 1;
+  for (int s = 0; s < lr; s++) {
+    const uint32_t hmask = (1u << s) - 1;
+    for (int b = threadIdx.x; b < nb; b += NT) {
+      const uint32_t c = b & cmask;
+      const uint32_t q = (uint32_t)b >> lc;
+      const uint32_t k = ((q >> s) << (s + 1)) | (q & hmask);
+      const uint32_t i1 = (k << lc) | c;
+      const uint32_t i2 = i1 + (1u << (s + lc));
+      const uint32_t w = tw[(1u << (s + rs)) + colbase + c + ((q & hmask) << rs)];
+      const uint32_t u = X[i1];
+      const uint32_t v = mmul(X[i2], w, md);
+      X[i1] = madd(u, v, md.P);
+      X[i2] = msub(u, v, md.P);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Task bodies.  Every thread of the workgroup calls them (they contain
+// barriers); X is the workgroup's LDS buffer of kLdsWords words.
+// ---------------------------------------------------------------------------
+
+// Whole product with N = 2^n <= 2^13: zero-padded loads, b scaled by R/N on
+// load, forward transforms of both, pointwise REDC (which removes one R and
+// leaves a b / N), inverse transform, store of the da + db + 1 coefficients.
+template <int NT>
+__device__ void exec_small_poly(const PrimeDev& pr, int n, const uint32_t* a, uint32_t da, const uint32_t* b,
+                                uint32_t db, uint32_t* out, uint32_t* X) {
+  const Mod md = mod_of(pr);
+  const uint32_t N = 1u << n;
+  uint32_t* A = X;
+  uint32_t* B = X + N;
+  const uint32_t sc = pr.s2[n];
+  for (uint32_t e = threadIdx.x; e < N; e += NT) {
+    A[e] = e <= da ? a[e] : 0u;
+    B[e] = e <= db ? mmul(b[e], sc, md) : 0u;
+  }
+  __syncthreads();
+  if (n > 0) lds_dif<NT, 2>(A, (int)N, n, 0, 0, 0, pr.twf, md);
+  for (uint32_t e = threadIdx.x; e < N; e += NT) A[e] = mmul(A[e], B[e], md);
+  __syncthreads();
+  if (n > 0) lds_dit<NT>(A, n, 0, 0, 0, pr.twi, md);
+  const uint32_t nout = da + db + 1;
+  for (uint32_t e = threadIdx.x; e < nout; e += NT) out[e] = A[e];
+  __syncthreads();
+}
+
+// Forward column pass, tile t: rows k < 2^n1, columns t*C + c; the input is
+// zero beyond index dvalid; scale != 0 multiplies by REDC(x * scale) on load.
+template <int NT>
+__device__ void exec_col_dif(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t dvalid,
+                             uint32_t scale, uint32_t* dst, uint32_t* X) {
+  const Mod md = mod_of(pr);
+  const int n1 = n - kRowLog;
+  const uint32_t colbase = t << lc;
+  const uint32_t cnt = 1u << (n1 + lc);
+  const uint32_t cmask = (1u << lc) - 1;
+  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+    const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+    uint32_t v = i <= dvalid ? src[i] : 0u;
+    if (scale) v = mmul(v, scale, md);
+    X[e] = v;
+  }
+  __syncthreads();
+  lds_dif<NT, 1>(X, 0, n1, lc, kRowLog, colbase, pr.twf, md);
+  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+    const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+    dst[i] = X[e];
+  }
+  __syncthreads();
+}
+
+// Inverse column pass, tile t: the last n1 inverse stages; stores only
+// indices < nout.
+template <int NT>
+__device__ void exec_col_dit(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t* dst,
+                             uint32_t nout, uint32_t* X) {
+  const Mod md = mod_of(pr);
+  const int n1 = n - kRowLog;
+  const uint32_t colbase = t << lc;
+  const uint32_t cnt = 1u << (n1 + lc);
+  const uint32_t cmask = (1u << lc) - 1;
+  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+    const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+    X[e] = src[i];
+  }
+  __syncthreads();
+  lds_dit<NT>(X, n1, lc, kRowLog, colbase, pr.twi, md);
+  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+    const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+    if (i < nout) dst[i] = X[e];
+  }
+  __syncthreads();
+}
+
+enum RowMode { ROW_POLY = 0, ROW_FWD = 1, ROW_INV = 2 };
+
+// Row pass over one contiguous block of 2^lr residues (block offsets are
+// multiples of 2^lr, so the twiddle index needs no column term).
+//   ROW_POLY: forward stages on A and B, A = REDC(A B), inverse stages on A;
+//   ROW_FWD:  forward stages on A;
+//   ROW_INV:  A scaled by REDC(x * prescale) on load, inverse stages on A.
+template <int NT>
+__device__ void exec_row(const PrimeDev& pr, int lr, int mode, uint32_t* gA, const uint32_t* gB,
+                         uint32_t prescale, uint32_t* X) {
+  const Mod md = mod_of(pr);
+  const uint32_t L = 1u << lr;
+  uint32_t* A = X;
+  uint32_t* B = X + L;
+  for (uint32_t e = threadIdx.x; e < L; e += NT) {
+    uint32_t v = gA[e];
+    if (mode == ROW_INV && prescale) v = mmul(v, prescale, md);
+    A[e] = v;
+    if (mode == ROW_POLY) B[e] = gB[e];
+  }
+  __syncthreads();
+  if (lr > 0) {
+    if (mode == ROW_POLY) lds_dif<NT, 2>(A, (int)L, lr, 0, 0, 0, pr.twf, md);
+    else if (mode == ROW_FWD) lds_dif<NT, 1>(A, 0, lr, 0, 0, 0, pr.twf, md);
+  }
+  if (mode == ROW_POLY) {
+    for (uint32_t e = threadIdx.x; e < L; e += NT) A[e] = mmul(A[e], B[e], md);
+    __syncthreads();
+  }
+  if (mode != ROW_FWD && lr > 0) lds_dit<NT>(A, lr, 0, 0, 0, pr.twi, md);
+  for (uint32_t e = threadIdx.x; e < L; e += NT) gA[e] = A[e];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+
+constexpr int kThreads = 512;
+
+// Plain launches: one task per workgroup, the task index is blockIdx.x.
+struct DirectArgs {
+  const PrimeDev* primes;
+  uint32_t prime_id, kind, n, lc;
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t* out;
+  uint32_t* scr;        // 2N words for the multi-pass product
+  uint32_t da, db;
+  uint32_t ntiles;
+  uint32_t prescale;
+};
+
+enum DirectKind : uint32_t {
+  D_SMALL_POLY = 0,  // grid 1
+  D_COLF = 1,        // grid 2 ntiles: tiles of a, then of b (scaled)
+  D_ROW_POLY = 2,    // grid nblocks
+  D_COLI = 3,        // grid ntiles
+  D_FWD_SMALL = 4,   // in place on out, grid 1
+  D_INV_SMALL = 5,   // in place on out, grid 1, prescale = s1[n]
+  D_COLF_INPLACE = 6,
+  D_ROW_FWD = 7,
+  D_ROW_INV = 8,
+  D_COLI_INPLACE = 9,
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ntt_direct(DirectArgs g) {
+  __shared__ uint32_t X[kLdsWords];
+  const PrimeDev& pr = g.primes[g.prime_id];
+  const uint32_t bid = blockIdx.x;
+  const uint32_t N = 1u << g.n;
+  const uint32_t S = 1u << kRowLog;
+  switch (g.kind) {
+    case D_SMALL_POLY: exec_small_poly<NT>(pr, g.n, g.a, g.da, g.b, g.db, g.out, X); break;
+    case D_COLF:
+      if (bid < g.ntiles) exec_col_dif<NT>(pr, g.n, g.lc, bid, g.a, g.da, 0u, g.scr, X);
+      else exec_col_dif<NT>(pr, g.n, g.lc, bid - g.ntiles, g.b, g.db, pr.s2[g.n], g.scr + N, X);
+      break;
+    case D_ROW_POLY: exec_row<NT>(pr, kRowLog, ROW_POLY, g.scr + bid * S, g.scr + N + bid * S, 0u, X); break;
+    case D_COLI: exec_col_dit<NT>(pr, g.n, g.lc, bid, g.scr, g.out, g.da + g.db + 1, X); break;
+    case D_FWD_SMALL: exec_row<NT>(pr, g.n, ROW_FWD, g.out, nullptr, 0u, X); break;
+    case D_INV_SMALL: exec_row<NT>(pr, g.n, ROW_INV, g.out, nullptr, g.prescale, X); break;
+    case D_COLF_INPLACE: exec_col_dif<NT>(pr, g.n, g.lc, bid, g.out, N - 1, 0u, g.out, X); break;
+    case D_ROW_FWD: exec_row<NT>(pr, kRowLog, ROW_FWD, g.out + bid * S, nullptr, 0u, X); break;
+    case D_ROW_INV: exec_row<NT>(pr, kRowLog, ROW_INV, g.out + bid * S, nullptr, g.prescale, X); break;
+    default: exec_col_dit<NT>(pr, g.n, g.lc, bid, g.out, g.out, N, X); break;
+  }
+}
+
+// Persistent batch kernel: workgroups take task indices from a counter in
+// the scratch header; a task's prerequisites always sit earlier in the list,
+// so every wait is on a task some running workgroup already holds.  Waits are
+// bounded by spin_limit sleeps; on expiry the status word is set, the task is
+// skipped, and so are all later waits, so the grid always drains.
+struct PlanArgs {
+  const PrimeDev* primes;
+  const ProdDev* prods;
+  const uint2* tasks;       // (product, kind << 28 | index)
+  uint32_t ntasks;
+  uint32_t nprods;
+  const uint32_t* in;
+  uint32_t* out;
+  uint32_t* scr;            // header, two counters per product, then product scratch
+  uint32_t spin_limit;
+};
+
+__device__ __forceinline__ bool wait_count(uint32_t* ctr, uint32_t need, uint32_t* status, uint32_t spin_limit) {
+  uint32_t it = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (++it > spin_limit) {
+      __hip_atomic_store(status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+  return true;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_ntt_persistent(PlanArgs g) {
+  __shared__ uint32_t X[kLdsWords];
+  __shared__ uint32_t s_task, s_go;
+  uint32_t* head = g.scr;
+  uint32_t* status = g.scr + 1;
+  uint32_t* cnt_col = g.scr + kHdrWords;
+  uint32_t* cnt_row = cnt_col + g.nprods;
+  const uint32_t S = 1u << kRowLog;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t ti = s_task;
+    if (ti >= g.ntasks) break;
+    const uint2 tk = g.tasks[ti];
+    const uint32_t p = tk.x;
+    const uint32_t kind = tk.y >> 28;
+    const uint32_t idx = tk.y & 0x0FFFFFFFu;
+    const ProdDev pd = g.prods[p];
+    const PrimeDev& pr = g.primes[pd.prime_id];
+    const uint32_t N = 1u << pd.n;
+    uint32_t* scr = g.scr + pd.scr_off;
+    if (threadIdx.x == 0) {
+      bool go = true;
+      if (kind == T_ROW) go = wait_count(cnt_col + p, 2 * pd.ntiles, status, g.spin_limit);
+      else if (kind == T_COLI) go = wait_count(cnt_row + p, pd.nblocks, status, g.spin_limit);
+      s_go = go ? 1u : 0u;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (s_go) {
+      switch (kind) {
+        case T_SMALL:
+          exec_small_poly<NT>(pr, pd.n, g.in + pd.a_off, pd.da, g.in + pd.b_off, pd.db, g.out + pd.c_off, X);
+          break;
+        case T_COLF_A: exec_col_dif<NT>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X); break;
+        case T_COLF_B:
+          exec_col_dif<NT>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X);
+          break;
+        case T_ROW: exec_row<NT>(pr, kRowLog, ROW_POLY, scr + idx * S, scr + N + idx * S, 0u, X); break;
+        default: exec_col_dit<NT>(pr, pd.n, pd.lc, idx, scr, g.out + pd.c_off, pd.da + pd.db + 1, X); break;
+      }
+      if (kind != T_SMALL && kind != T_COLI) {
+        // Publish this task's stores at agent scope before counting it.
+        __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          uint32_t* ctr = kind == T_ROW ? cnt_row + p : cnt_col + p;
+          __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Zero the scratch header and counters (a kernel, not a memset, so that the
+// sequence can be captured in a graph).
+__global__ void k_fill_zero(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// Twiddle generation.  pw[b] = residue of w^(2^b) by repeated squaring of
+// the residue of w (one lane), then every table entry is a product of those.
+__global__ void k_tw_pows(uint32_t P, uint32_t Pp, uint32_t R2, uint32_t w, uint32_t L, uint32_t* pw) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const Mod md{P, Pp};
+    uint32_t x = mmul(w, R2, md);
+    for (uint32_t b = 0; b < L; b++) {
+      pw[b] = x;
+      x = mmul(x, x, md);
+    }
+  }
+}
+
+__global__ void k_tw_fill(uint32_t P, uint32_t Pp, uint32_t R1, uint32_t L, const uint32_t* pw, uint32_t* twf,
+                          uint32_t* twi) {
+  const Mod md{P, Pp};
+  const uint32_t Nmax = 1u << L;
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < Nmax; x += gridDim.x * blockDim.x) {
+    if (x == 0) {
+      twf[0] = 0u;
+      twi[0] = 0u;
+      continue;
+    }
+    const uint32_t s = 31u - __builtin_clz(x);          // h = 2^s
+    const uint32_t i = x - (1u << s);
+    const uint32_t ef = i << (L - 1 - s);               // w_{2h}^i = w^(i Nmax / 2h)
+    const uint32_t ei = (Nmax - ef) & (Nmax - 1);       // w^-e = w^(Nmax - e)
+    uint32_t f = R1, v = R1;
+    for (uint32_t b = 0; b < L; b++) {
+      if ((ef >> b) & 1u) f = mmul(f, pw[b], md);
+      if ((ei >> b) & 1u) v = mmul(v, pw[b], md);
+    }
+    twf[x] = f;
+    twi[x] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+
+uint32_t powmod_host(uint64_t x, uint64_t e, uint32_t P) {
+  uint64_t r = 1 % P;
+  x %= P;
+  while (e) {
+    if (e & 1) r = r * x % P;
+    x = x * x % P;
+    e >>= 1;
+  }
+  return (uint32_t)r;
+}
+
+// Smallest primitive root of prime P (0 if P is not prime).
+uint32_t primitive_root_host(uint32_t P) {
+  std::vector<uint32_t> qs;
+  uint32_t m = P - 1;
+  for (uint32_t f = 2; (uint64_t)f * f <= m; f++)
+    if (m % f == 0) {
+      qs.push_back(f);
+      while (m % f == 0) m /= f;
+    }
+  if (m > 1) qs.push_back(m);
+  for (uint32_t g = 2; g < P; g++) {
+    bool ok = true;
+    for (uint32_t q : qs)
+      if (powmod_host(g, (P - 1) / q, P) == 1) {
+        ok = false;
+        break;
+      }
+    if (ok) return g;
+  }
+  return 0;
+}
+
+bool is_prime_host(uint32_t P) {
+  if (P < 2) return false;
+  for (uint32_t f = 2; (uint64_t)f * f <= P; f++)
+    if (P % f == 0) return false;
+  return true;
+}
+
+int ceil_log2(uint64_t x) {
+  int n = 0;
+  while (((uint64_t)1 << n) < x) n++;
+  return n;
+}
+
+// Column-tile width for a multi-pass length 2^n: as many adjacent columns as
+// fit 2^14 residues of LDS, at most the 2^13 columns there are.
+int col_lc(int n) { return std::min(kRowLog, 14 - (n - kRowLog)); }
+
+}  // namespace
+
+}  // namespace mont
+
+using namespace mont;
+
+struct ntt_ctx {
+  int device = 0;
+  int log2_nmax = 0;
+  std::vector<mont_params> params;
+  std::vector<uint32_t> roots;      // w of order 2^logmax_p (ordinary residue)
+  std::vector<uint32_t> logmax;
+  std::vector<uint32_t*> twf, twi;  // device pointers into tw_mem
+  PrimeDev* d_primes = nullptr;
+  uint32_t* tw_mem = nullptr;
+};
+
+struct ntt_plan {
+  const ntt_ctx* ctx = nullptr;
+  int count = 0;
+  uint32_t ntasks = 0;
+  uint64_t scratch_words = 0;
+  uint64_t in_words = 0, out_words = 0;
+  ProdDev* d_prods = nullptr;
+  uint2* d_tasks = nullptr;
+  int default_grid = 0;
+};
+
+namespace {
+
+mont_status hip_ok(hipError_t e) { return e == hipSuccess ? MONT_OK : MONT_EHIP; }
+
+void launch_direct(const DirectArgs& g, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_ntt_direct<kThreads>), dim3(grid), dim3(kThreads), 0, s, g);
+}
+
+bool prime_ok(const ntt_ctx* ctx, int prime_id) {
+  return ctx && prime_id >= 0 && prime_id < (int)ctx->params.size();
+}
+
+DirectArgs direct_base(const ntt_ctx* ctx, int prime_id, int n) {
+  DirectArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.primes = ctx->d_primes;
+  g.prime_id = (uint32_t)prime_id;
+  g.n = (uint32_t)n;
+  if (n > kRowLog) {
+    g.lc = (uint32_t)col_lc(n);
+    g.ntiles = 1u << (kRowLog - g.lc);
+  }
+  return g;
+}
+
+}  // namespace
+
+extern "C" mont_status ntt_ctx_create(const uint32_t* primes, int nprimes, int log2_nmax, ntt_ctx** out) {
+  if (!out || !primes || nprimes <= 0 || nprimes > 64 || log2_nmax < 1 || log2_nmax > kMaxLog) return MONT_EINVAL;
+  *out = nullptr;
+  ntt_ctx* ctx = new (std::nothrow) ntt_ctx;
+  if (!ctx) return MONT_ENOMEM;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    delete ctx;
+    return MONT_EHIP;
+  }
+  ctx->log2_nmax = log2_nmax;
+  uint64_t total = 0;
+  for (int i = 0; i < nprimes; i++) {
+    mont_params prm;
+    if (mont_setup(primes[i], &prm) != MONT_OK || !is_prime_host(primes[i])) {
+      delete ctx;
+      return MONT_EINVAL;
+    }
+    uint32_t L = std::min<uint32_t>((uint32_t)log2_nmax, prm.k);
+    ctx->params.push_back(prm);
+    ctx->logmax.push_back(L);
+    uint32_t g = primitive_root_host(prm.P);
+    ctx->roots.push_back(powmod_host(g, (prm.P - 1) >> L, prm.P));
+    total += 2ull << L;
+  }
+  total += 32ull * nprimes;  // per-prime power tables
+  if (hipMalloc(&ctx->tw_mem, total * 4) != hipSuccess) {
+    delete ctx;
+    return MONT_ENOMEM;
+  }
+  if (hipMalloc(&ctx->d_primes, sizeof(PrimeDev) * nprimes) != hipSuccess) {
+    (void)hipFree(ctx->tw_mem);
+    delete ctx;
+    return MONT_ENOMEM;
+  }
+  std::vector<PrimeDev> hp(nprimes);
+  uint32_t* cur = ctx->tw_mem;
+  uint32_t* pw = ctx->tw_mem + (total - 32ull * nprimes);
+  mont_status st = MONT_OK;
+  for (int i = 0; i < nprimes && st == MONT_OK; i++) {
+    const mont_params& prm = ctx->params[i];
+    uint32_t L = ctx->logmax[i];
+    PrimeDev& d = hp[i];
+    std::memset(&d, 0, sizeof(d));
+    d.P = prm.P;
+    d.Pp = prm.Pprime;
+    d.R1 = prm.R1;
+    d.R2 = prm.R2;
+    d.logmax = L;
+    uint32_t* f = cur;
+    uint32_t* v = cur + (1u << L);
+    cur += 2ull << L;
+    d.twf = f;
+    d.twi = v;
+    ctx->twf.push_back(f);
+    ctx->twi.push_back(v);
+    for (uint32_t n = 0; n <= L; n++) {
+      // N^-1 = P - (P-1)/N because N (P-1)/N = P - 1 = -1 (mod P)
+      uint64_t ninv = prm.P - ((prm.P - 1) >> n);
+      d.s1[n] = (uint32_t)((uint64_t)prm.R1 * ninv % prm.P);
+      d.s2[n] = (uint32_t)((uint64_t)prm.R2 * ninv % prm.P);
+    }
+    hipLaunchKernelGGL(k_tw_pows, dim3(1), dim3(64), 0, 0, prm.P, prm.Pprime, prm.R2, ctx->roots[i], L, pw + 32 * i);
+    uint32_t blocks = std::max(1u, std::min(4096u, (1u << L) / 256));
+    hipLaunchKernelGGL(k_tw_fill, dim3(blocks), dim3(256), 0, 0, prm.P, prm.Pprime, prm.R1, L, pw + 32 * i, f, v);
+    st = last_launch_status();
+  }
+  if (st == MONT_OK) st = hip_ok(hipMemcpy(ctx->d_primes, hp.data(), sizeof(PrimeDev) * nprimes,
+                                           hipMemcpyHostToDevice));
+  if (st == MONT_OK) st = hip_ok(hipDeviceSynchronize());
+  if (st != MONT_OK) {
+    (void)hipFree(ctx->tw_mem);
+    (void)hipFree(ctx->d_primes);
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_ctx_destroy(ntt_ctx* ctx) {
+  if (!ctx) return MONT_EINVAL;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ctx->tw_mem);
+  (void)hipFree(ctx->d_primes);
+  delete ctx;
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_ctx_prime(const ntt_ctx* ctx, int prime_id, mont_params* prm, uint32_t* root,
+                                     uint32_t* log2_max, const uint32_t** d_twf, const uint32_t** d_twi) {
+  if (!prime_ok(ctx, prime_id)) return MONT_EINVAL;
+  if (prm) *prm = ctx->params[prime_id];
+  if (root) *root = ctx->roots[prime_id];
+  if (log2_max) *log2_max = ctx->logmax[prime_id];
+  if (d_twf) *d_twf = ctx->twf[prime_id];
+  if (d_twi) *d_twi = ctx->twi[prime_id];
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_ctx_read_twiddles(const ntt_ctx* ctx, int prime_id, uint32_t* h_fwd, uint32_t* h_inv) {
+  if (!prime_ok(ctx, prime_id) || !h_fwd || !h_inv) return MONT_EINVAL;
+  size_t bytes = (size_t)4 << ctx->logmax[prime_id];
+  if (hipMemcpy(h_fwd, ctx->twf[prime_id], bytes, hipMemcpyDeviceToHost) != hipSuccess) return MONT_EHIP;
+  if (hipMemcpy(h_inv, ctx->twi[prime_id], bytes, hipMemcpyDeviceToHost) != hipSuccess) return MONT_EHIP;
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_forward(const ntt_ctx* ctx, int prime_id, uint32_t* d_x, uint32_t log2n, void* stream) {
+  if (!prime_ok(ctx, prime_id) || !d_x) return MONT_EINVAL;
+  if (log2n > ctx->logmax[prime_id]) return MONT_ENOROOT;
+  hipStream_t s = as_stream(stream);
+  (void)hipGetLastError();
+  int n = (int)log2n;
+  DirectArgs g = direct_base(ctx, prime_id, n);
+  g.out = d_x;
+  if (n <= kRowLog) {
+    g.kind = D_FWD_SMALL;
+    launch_direct(g, 1, s);
+  } else {
+    g.kind = D_COLF_INPLACE;
+    launch_direct(g, g.ntiles, s);
+    g.kind = D_ROW_FWD;
+    launch_direct(g, 1u << (n - kRowLog), s);
+  }
+  return last_launch_status();
+}
+
+extern "C" mont_status ntt_inverse(const ntt_ctx* ctx, int prime_id, uint32_t* d_x, uint32_t log2n, void* stream) {
+  if (!prime_ok(ctx, prime_id) || !d_x) return MONT_EINVAL;
+  if (log2n > ctx->logmax[prime_id]) return MONT_ENOROOT;
+  hipStream_t s = as_stream(stream);
+  (void)hipGetLastError();
+  int n = (int)log2n;
+  const mont_params& prm = ctx->params[prime_id];
+  uint64_t ninv = prm.P - ((prm.P - 1) >> n);
+  DirectArgs g = direct_base(ctx, prime_id, n);
+  g.out = d_x;
+  g.prescale = (uint32_t)((uint64_t)prm.R1 * ninv % prm.P);
+  if (n <= kRowLog) {
+    g.kind = D_INV_SMALL;
+    launch_direct(g, 1, s);
+  } else {
+    g.kind = D_ROW_INV;
+    launch_direct(g, 1u << (n - kRowLog), s);
+    g.kind = D_COLI_INPLACE;
+    launch_direct(g, g.ntiles, s);
+  }
+  return last_launch_status();
+}
+
+extern "C" size_t ntt_polymul_scratch_bytes(uint32_t da, uint32_t db) {
+  int n = ceil_log2((uint64_t)da + db + 1);
+  return n <= kRowLog ? 0 : (size_t)8 << n;
+}
+
+extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint32_t* d_a, uint32_t da,
+                                   const uint32_t* d_b, uint32_t db, uint32_t* d_out, void* d_scratch,
+                                   size_t scratch_bytes, void* stream) {
+  if (!prime_ok(ctx, prime_id) || !d_a || !d_b || !d_out) return MONT_EINVAL;
+  if ((uint64_t)da + db + 1 > ((uint64_t)1 << 31)) return MONT_ERANGE;
+  int n = ceil_log2((uint64_t)da + db + 1);
+  if ((uint32_t)n > ctx->logmax[prime_id]) return MONT_ENOROOT;
+  size_t need = ntt_polymul_scratch_bytes(da, db);
+  if (need && (!d_scratch || scratch_bytes < need)) return MONT_ENOMEM;
+  hipStream_t s = as_stream(stream);
+  (void)hipGetLastError();
+  DirectArgs g = direct_base(ctx, prime_id, n);
+  g.a = d_a;
+  g.b = d_b;
+  g.da = da;
+  g.db = db;
+  g.out = d_out;
+  g.scr = static_cast<uint32_t*>(d_scratch);
+  if (n <= kRowLog) {
+    g.kind = D_SMALL_POLY;
+    launch_direct(g, 1, s);
+  } else {
+    g.kind = D_COLF;
+    launch_direct(g, 2 * g.ntiles, s);
+    g.kind = D_ROW_POLY;
+    launch_direct(g, 1u << (n - kRowLog), s);
+    g.kind = D_COLI;
+    launch_direct(g, g.ntiles, s);
+  }
+  return last_launch_status();
+}
+
+// ---------------------------------------------------------------------------
+// Batch plans.
+// ---------------------------------------------------------------------------
+
+extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
+                                       ntt_plan** out) {
+  if (!ctx || !out || count < 0 || (count > 0 && !descs)) return MONT_EINVAL;
+  *out = nullptr;
+  std::vector<ProdDev> prods(count);
+  std::vector<uint2> colf, small, row, coli;
+  uint64_t scr = kHdrWords + 2ull * count;
+  scr = (scr + 63) & ~63ull;
+  uint64_t in_words = 0, out_words = 0;
+  for (int p = 0; p < count; p++) {
+    const polymul_desc& d = descs[p];
+    if (d.prime_id >= ctx->params.size()) return MONT_EINVAL;
+    uint64_t nout = (uint64_t)d.da + d.db + 1;
+    if (nout > ((uint64_t)1 << 31)) return MONT_ERANGE;
+    int n = ceil_log2(nout);
+    if ((uint32_t)n > ctx->logmax[d.prime_id]) return MONT_ENOROOT;
+    ProdDev& pd = prods[p];
+    std::memset(&pd, 0, sizeof(pd));
+    pd.prime_id = d.prime_id;
+    pd.n = (uint32_t)n;
+    pd.da = d.da;
+    pd.db = d.db;
+    pd.a_off = d.a_off;
+    pd.b_off = d.b_off;
+    pd.c_off = d.c_off;
+    in_words = std::max<uint64_t>(in_words, std::max(d.a_off + d.da + 1, d.b_off + d.db + 1));
+    out_words = std::max<uint64_t>(out_words, d.c_off + nout);
+    if (n <= kRowLog) {
+      small.push_back(make_uint2((uint32_t)p, T_SMALL << 28));
+    } else {
+      pd.lc = (uint32_t)col_lc(n);
+      pd.ntiles = 1u << (kRowLog - pd.lc);
+      pd.nblocks = 1u << (n - kRowLog);
+      pd.scr_off = scr;
+      scr += 2ull << n;
+    }
+  }
+  // Cost order: longest products first within each group.
+  std::vector<int> big;
+  for (int p = 0; p < count; p++)
+    if (prods[p].n > (uint32_t)kRowLog) big.push_back(p);
+  std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return prods[x].n > prods[y].n; });
+  std::stable_sort(small.begin(), small.end(), [&](uint2 x, uint2 y) { return prods[x.x].n > prods[y.x].n; });
+  for (int p : big) {
+    const ProdDev& pd = prods[p];
+    for (uint32_t t = 0; t < pd.ntiles; t++) colf.push_back(make_uint2((uint32_t)p, (T_COLF_A << 28) | t));
+    for (uint32_t t = 0; t < pd.ntiles; t++) colf.push_back(make_uint2((uint32_t)p, (T_COLF_B << 28) | t));
+    for (uint32_t j = 0; j < pd.nblocks; j++) row.push_back(make_uint2((uint32_t)p, (T_ROW << 28) | j));
+    for (uint32_t t = 0; t < pd.ntiles; t++) coli.push_back(make_uint2((uint32_t)p, (T_COLI << 28) | t));
+  }
+  if (order_seed != 0) {
+    // Any order within a group keeps prerequisites earlier in the list.
+    std::mt19937_64 rng(order_seed);
+    std::shuffle(colf.begin(), colf.end(), rng);
+    std::shuffle(small.begin(), small.end(), rng);
+    std::shuffle(row.begin(), row.end(), rng);
+    std::shuffle(coli.begin(), coli.end(), rng);
+  }
+  std::vector<uint2> tasks;
+  tasks.reserve(colf.size() + small.size() + row.size() + coli.size());
+  size_t half = small.size() / 2;
+  tasks.insert(tasks.end(), colf.begin(), colf.end());
+  tasks.insert(tasks.end(), small.begin(), small.begin() + half);
+  tasks.insert(tasks.end(), row.begin(), row.end());
+  tasks.insert(tasks.end(), small.begin() + half, small.end());
+  tasks.insert(tasks.end(), coli.begin(), coli.end());
+
+  ntt_plan* plan = new (std::nothrow) ntt_plan;
+  if (!plan) return MONT_ENOMEM;
+  plan->ctx = ctx;
+  plan->count = count;
+  plan->ntasks = (uint32_t)tasks.size();
+  plan->scratch_words = scr;
+  plan->in_words = in_words;
+  plan->out_words = out_words;
+  if (count > 0) {
+    if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * count) != hipSuccess ||
+        hipMalloc(&plan->d_tasks, sizeof(uint2) * std::max<size_t>(1, tasks.size())) != hipSuccess) {
+      (void)hipFree(plan->d_prods);
+      delete plan;
+      return MONT_ENOMEM;
+    }
+    if (hipMemcpy(plan->d_prods, prods.data(), sizeof(ProdDev) * count, hipMemcpyHostToDevice) != hipSuccess ||
+        (tasks.size() && hipMemcpy(plan->d_tasks, tasks.data(), sizeof(uint2) * tasks.size(),
+                                   hipMemcpyHostToDevice) != hipSuccess)) {
+      (void)hipFree(plan->d_prods);
+      (void)hipFree(plan->d_tasks);
+      delete plan;
+      return MONT_EHIP;
+    }
+  }
+  int dev = 0, cus = 256, per_cu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ntt_persistent<kThreads>, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  plan->default_grid = cus * per_cu;
+  *out = plan;
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, uint32_t* ntasks,
+                                     uint64_t* in_words, uint64_t* out_words, int* default_grid) {
+  if (!plan) return MONT_EINVAL;
+  if (scratch_bytes) *scratch_bytes = (size_t)plan->scratch_words * 4;
+  if (ntasks) *ntasks = plan->ntasks;
+  if (in_words) *in_words = plan->in_words;
+  if (out_words) *out_words = plan->out_words;
+  if (default_grid) *default_grid = plan->default_grid;
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_in, uint32_t* d_out, void* d_scratch,
+                                        size_t scratch_bytes, int grid, uint32_t spin_limit, void* stream) {
+  if (!plan) return MONT_EINVAL;
+  if (plan->count == 0) return MONT_OK;
+  if (!d_in || !d_out || !d_scratch) return MONT_EINVAL;
+  if (scratch_bytes < plan->scratch_words * 4) return MONT_ENOMEM;
+  if (grid < 0) return MONT_EINVAL;
+  hipStream_t s = as_stream(stream);
+  (void)hipGetLastError();
+  uint32_t* scr = static_cast<uint32_t*>(d_scratch);
+  uint32_t nz = (uint32_t)(kHdrWords + 2ull * plan->count);
+  hipLaunchKernelGGL(k_fill_zero, dim3(std::min(1024u, (nz + 255) / 256)), dim3(256), 0, s, scr, nz);
+  PlanArgs g;
+  g.primes = plan->ctx->d_primes;
+  g.prods = plan->d_prods;
+  g.tasks = plan->d_tasks;
+  g.ntasks = plan->ntasks;
+  g.nprods = (uint32_t)plan->count;
+  g.in = d_in;
+  g.out = d_out;
+  g.scr = scr;
+  g.spin_limit = spin_limit ? spin_limit : (1u << 24);
+  uint32_t gsz = grid > 0 ? (uint32_t)grid : (uint32_t)plan->default_grid;
+  gsz = std::max(1u, std::min(gsz, plan->ntasks));
+  hipLaunchKernelGGL((k_ntt_persistent<kThreads>), dim3(gsz), dim3(kThreads), 0, s, g);
+  return last_launch_status();
+}
+
+extern "C" mont_status ntt_plan_status(const ntt_plan* plan, const void* d_scratch, void* stream) {
+  if (!plan || !d_scratch) return MONT_EINVAL;
+  if (plan->count == 0) return MONT_OK;
+  hipStream_t s = as_stream(stream);
+  uint32_t st = 0;
+  if (hipMemcpyAsync(&st, static_cast<const uint32_t*>(d_scratch) + 1, 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return MONT_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MONT_EHIP;
+  return st == 0 ? MONT_OK : MONT_ETIMEOUT;
+}
+
+extern "C" mont_status ntt_plan_destroy(ntt_plan* plan) {
+  if (!plan) return MONT_EINVAL;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(plan->d_prods);
+  (void)hipFree(plan->d_tasks);
+  delete plan;
+  return MONT_OK;
+}

@@ -94,3 +94,26 @@ def test_elem_tune(L):
         assert L.mont_elem_tune_set(9, 256, 1, 1) == -1
     finally:
         mont.elem_tune_set("mul", *old)
+
+
+def test_ntt_host_validation(L):
+    import ctypes as C
+    from paper_1609_00999_amd import ntt  # noqa: F401  (registers argument types)
+    h = C.c_void_p()
+    arr = (C.c_uint32 * 1)(2013265921)
+    assert L.ntt_ctx_create(arr, 0, 23, C.byref(h)) == -1
+    assert L.ntt_ctx_create(arr, 1, 0, C.byref(h)) == -1
+    assert L.ntt_ctx_create(arr, 1, 28, C.byref(h)) == -1
+    assert L.ntt_ctx_create(None, 1, 23, C.byref(h)) == -1
+    assert L.ntt_ctx_create(arr, 1, 23, None) == -1
+    assert L.ntt_ctx_destroy(None) == -1
+    assert L.ntt_forward(None, 0, 16, 4, None) == -1
+    assert L.ntt_polymul(None, 0, 16, 1, 16, 1, 16, None, 0, None) == -1
+    assert L.ntt_plan_create(None, None, 0, 0, C.byref(h)) == -1
+    assert L.ntt_plan_execute(None, None, None, None, 0, 0, 0, None) == -1
+    assert L.ntt_plan_destroy(None) == -1
+    # scratch sizing is pure host arithmetic
+    assert L.ntt_polymul_scratch_bytes(0, 0) == 0
+    assert L.ntt_polymul_scratch_bytes(4095, 4096) == 0          # N = 2^13: one workgroup
+    assert L.ntt_polymul_scratch_bytes(4096, 4096) == 8 << 14    # N = 2^14: two arrays of N words
+    assert L.ntt_polymul_scratch_bytes((1 << 20) - 1, (1 << 20) - 1) == 8 << 21

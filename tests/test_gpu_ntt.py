@@ -1,0 +1,289 @@
+"""GPU parity of the transforms, single polynomial products and the persistent
+batch against the CPU oracle (bit-exact)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_00999_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PRIMES = wl.PRIMES_NTT
+
+
+@pytest.fixture(scope="module")
+def N():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1609_00999_amd import ntt
+    return ntt
+
+
+@pytest.fixture(scope="module")
+def ctx(N):
+    c = N.Context(PRIMES, 23)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def bitrev(n_log2):
+    n = 1 << n_log2
+    r = np.zeros(n, dtype=np.int64)
+    for b in range(n_log2):
+        r |= ((np.arange(n) >> b) & 1) << (n_log2 - 1 - b)
+    return r
+
+
+def test_context_roots_and_tables(ctx):
+    for pid, P in enumerate(PRIMES):
+        prm, root, lmax, _, _ = ctx.prime(pid)
+        ref = oracle.setup(P)
+        assert (prm.P, prm.Pprime, prm.R1, prm.R2) == (P, ref.Pprime, ref.R1, ref.R2)
+        assert lmax == 23
+        g = oracle.primitive_root(P)
+        assert root == pow(g, (P - 1) >> lmax, P)
+        assert pow(root, 1 << lmax, P) == 1 and pow(root, 1 << (lmax - 1), P) == P - 1
+        f, iv = ctx.twiddles(pid)
+        rng = np.random.default_rng(pid)
+        xs = np.unique(np.concatenate([np.arange(1, 70), rng.integers(1, 1 << lmax, 3000),
+                                       (1 << np.arange(lmax)), (1 << np.arange(1, lmax)) - 1]))
+        R = 1 << 32
+        for x in xs.tolist():
+            s = x.bit_length() - 1
+            i = x - (1 << s)
+            e = i << (lmax - 1 - s)
+            assert int(f[x]) == pow(root, e, P) * R % P, (pid, x)
+            assert int(iv[x]) == pow(root, (1 << lmax) - e, P) * R % P, (pid, x)
+
+
+@pytest.mark.parametrize("logn", [0, 1, 2, 5, 10, 12, 13, 14, 15, 17, 20, 23])
+def test_forward_inverse_vs_oracle(N, ctx, logn):
+    pid = logn % len(PRIMES)
+    P = PRIMES[pid]
+    n = 1 << logn
+    rng = np.random.default_rng(logn)
+    x = rng.integers(0, P, n, dtype=np.uint32)
+    dx = dev(x)
+    N.forward(ctx, pid, dx)
+    got = host(dx)
+    g = oracle.primitive_root(P)
+    w = pow(g, (P - 1) >> logn, P)
+    want = oracle.ntt(P, x, w)                 # natural order
+    assert np.array_equal(got, want[bitrev(logn)])
+    N.inverse(ctx, pid, dx)
+    assert np.array_equal(host(dx), x)
+    # inverse alone vs the oracle's transform with w^-1 and N^-1
+    y = rng.integers(0, P, n, dtype=np.uint32)
+    dy = dev(y)
+    N.inverse(ctx, pid, dy)
+    inv = oracle.ntt(P, y[bitrev(logn)], pow(w, P - 2, P)).astype(np.uint64)
+    inv = (inv * np.uint64(pow(n, P - 2, P))) % np.uint64(P)
+    assert np.array_equal(host(dy), inv.astype(np.uint32))
+
+
+SHAPES = [(0, 0), (0, 7), (5, 0), (1, 1), (255, 256), (2047, 2048), (4095, 4096), (4096, 4095),
+          (8191, 0), (4096, 4096), (6000, 2191), (8191, 8191), (12345, 54321), (65535, 65536), (100000, 3)]
+
+
+@pytest.mark.parametrize("da,db", SHAPES)
+def test_polymul_vs_oracle(N, ctx, da, db):
+    pid = (da + 3 * db) % len(PRIMES)
+    P = PRIMES[pid]
+    rng = np.random.default_rng(da * 7 + db)
+    a = rng.integers(0, P, da + 1, dtype=np.uint32)
+    b = rng.integers(0, P, db + 1, dtype=np.uint32)
+    got = host(N.polymul(ctx, pid, dev(a), dev(b)))
+    assert np.array_equal(got, oracle.polymul(P, a, b))
+
+
+def test_polymul_golden(N, ctx):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "polymul_small.txt")
+    for ln in open(path):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        v = [int(x) for x in ln.split()]
+        P, da, db = v[:3]
+        a = np.array(v[3:4 + da], dtype=np.uint32)
+        b = np.array(v[4 + da:5 + da + db], dtype=np.uint32)
+        c = np.array(v[5 + da + db:], dtype=np.uint32)
+        got = host(N.polymul(ctx, PRIMES.index(P), dev(a), dev(b)))
+        assert np.array_equal(got, c)
+
+
+def test_polymul_special_cases(N, ctx):
+    import math
+    P = PRIMES[4]
+    d = 20000
+    rng = np.random.default_rng(3)
+    b = rng.integers(0, P, d + 1, dtype=np.uint32)
+    one = np.array([1], dtype=np.uint32)
+    assert np.array_equal(host(N.polymul(ctx, 4, dev(one), dev(b))), b)
+    xk = np.zeros(1001, dtype=np.uint32)
+    xk[1000] = 1
+    c = host(N.polymul(ctx, 4, dev(xk), dev(b)))
+    assert np.all(c[:1000] == 0) and np.array_equal(c[1000:], b)
+    ones = np.ones(d + 1, dtype=np.uint32)
+    kk = np.arange(2 * d + 1)
+    assert np.array_equal(host(N.polymul(ctx, 4, dev(ones), dev(ones))),
+                          (np.minimum(kk, 2 * d - kk) + 1).astype(np.uint32))
+    dd = 3000
+    binom = np.array([math.comb(dd, k) % P for k in range(dd + 1)], dtype=np.uint32)
+    got = host(N.polymul(ctx, 4, dev(binom), dev(binom)))
+    assert got.tolist() == [math.comb(2 * dd, k) % P for k in range(2 * dd + 1)]
+
+
+def test_polymul_largest_length(N, ctx):
+    """N = 2^23, the longest transform the tables support: Schwartz-Zippel."""
+    d = (1 << 22) - 1
+    pid = 1
+    P = PRIMES[pid]
+    rng = np.random.default_rng(23)
+    a = rng.integers(0, P, d + 1, dtype=np.uint32)
+    b = rng.integers(0, P, d + 1, dtype=np.uint32)
+    c = host(N.polymul(ctx, pid, dev(a), dev(b)))
+    assert c.size == 2 * d + 1
+    for x in rng.integers(2, P, 3).tolist():
+        assert oracle.horner(P, c, x) == oracle.horner(P, a, x) * oracle.horner(P, b, x) % P
+
+
+def test_polymul_errors(N, ctx):
+    from paper_1609_00999_amd import mont
+    P = PRIMES[0]
+    a = dev(np.ones(10, dtype=np.uint32))
+    with pytest.raises(mont.MontError):
+        N.polymul(ctx, 99, a, a)
+    # a prime whose 2-adic valuation is too small for the length
+    small = N.Context([998244353, 469762049], 23)     # k = 23 and 26
+    try:
+        prm, _, lmax, _, _ = small.prime(0)
+        assert lmax == 23
+    finally:
+        small.close()
+    c2 = N.Context([2013265921], 12)
+    try:
+        x = dev(np.ones(1 << 13, dtype=np.uint32))
+        with pytest.raises(mont.MontError) as ei:
+            N.forward(c2, 0, x)
+        assert ei.value.status == -3
+        with pytest.raises(mont.MontError) as ei:
+            N.polymul(c2, 0, x, x)
+        assert ei.value.status == -3
+    finally:
+        c2.close()
+
+
+def small_batch(count, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    da = wl.log_uniform(rng, lo, hi, count)
+    db = np.maximum(0, da + rng.integers(-3, 4, count))
+    pid = rng.integers(0, len(PRIMES), count)
+    return wl.pack_products(PRIMES, pid, da, db, rng)
+
+
+def run_plan(N, ctx, batch, grid=0, order_seed=0, spin_limit=0):
+    plan = N.Plan.from_batch(ctx, batch, order_seed)
+    din = dev(batch.coeffs)
+    out = torch.zeros(max(1, batch.out_len), dtype=torch.int32, device="cuda")
+    scr = plan.alloc_scratch()
+    plan.execute(din, out, scr, grid=grid, spin_limit=spin_limit)
+    st = plan.status(scr)
+    res = host(out)
+    plan.close()
+    return st, res
+
+
+def oracle_batch(batch):
+    jobs = [batch.operands(i) for i in range(batch.count)]
+    res = oracle.polymul_many(jobs)
+    return np.concatenate(res)
+
+
+def test_batch_vs_oracle(N, ctx):
+    batch = small_batch(96, 0, 17, 41)
+    st, got = run_plan(N, ctx, batch)
+    assert st == 0
+    assert np.array_equal(got, oracle_batch(batch))
+
+
+def test_batch_grid_and_order_invariance(N, ctx):
+    batch = small_batch(64, 4, 18, 42)
+    ref = oracle_batch(batch)
+    outs = []
+    for grid, seed in [(0, 0), (1, 0), (3, 0), (0, 12345), (7, 999)]:
+        st, got = run_plan(N, ctx, batch, grid=grid, order_seed=seed)
+        assert st == 0
+        outs.append(got)
+        assert np.array_equal(got, ref), (grid, seed)
+    for o in outs[1:]:
+        assert o.tobytes() == outs[0].tobytes()
+
+
+def test_batch_empty_and_tiny(N, ctx):
+    b = wl.pack_products(PRIMES, [0], [0], [0], np.random.default_rng(0))
+    st, got = run_plan(N, ctx, b)
+    assert st == 0 and np.array_equal(got, oracle_batch(b))
+    empty = N.Plan(ctx, [], [], [], [], [], [])
+    assert empty.ntasks == 0
+    empty.close()
+
+
+def test_batch_timeout_path_drains(N, ctx):
+    """A one-sleep wait limit: waits that do not finish at once record a
+    timeout and the launch still drains; if no wait was needed the result is
+    exact."""
+    batch = small_batch(4, 17, 19, 43)
+    ref = oracle_batch(batch)
+    st, got = run_plan(N, ctx, batch, grid=0, spin_limit=1)
+    assert st in (0, -6)
+    if st == 0:
+        assert np.array_equal(got, ref)
+    # the next normal execution is exact again
+    st, got = run_plan(N, ctx, batch)
+    assert st == 0 and np.array_equal(got, ref)
+
+
+def test_batch_config_full_size(N, ctx):
+    """2048 products, degrees log-uniform in [2^8, 2^20), eight primes, one
+    persistent launch.  Every product is checked by Schwartz-Zippel at two
+    points; a sample is compared coefficient by coefficient."""
+    batch = wl.polymul_batch()
+    plan = N.Plan.from_batch(ctx, batch)
+    din = dev(batch.coeffs)
+    out = torch.empty(batch.out_len, dtype=torch.int32, device="cuda")
+    scr = plan.alloc_scratch()
+    plan.execute(din, out, scr)
+    assert plan.status(scr) == 0
+    got = host(out)
+    plan.close()
+    del scr, din
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(77)
+    pts = rng.integers(2, 1 << 30, (batch.count, 2))
+
+    def check(i):
+        P, a, b = batch.operands(i)
+        c = got[batch.c_off[i]: batch.c_off[i] + a.size + b.size - 1]
+        for x in pts[i].tolist():
+            if oracle.horner(P, c, x) != oracle.horner(P, a, x) * oracle.horner(P, b, x) % P:
+                return i
+        return -1
+
+    with ThreadPoolExecutor(oracle.default_threads()) as ex:
+        bad = [i for i in ex.map(check, range(batch.count)) if i >= 0]
+    assert not bad, bad[:10]
+    order = np.argsort(batch.da)
+    sample = list(order[:24]) + list(order[-3:]) + list(rng.choice(batch.count, 5, replace=False))
+    jobs = [batch.operands(i) for i in sample]
+    for i, ref in zip(sample, oracle.polymul_many(jobs)):
+        assert np.array_equal(got[batch.c_off[i]: batch.c_off[i] + ref.size], ref), i
