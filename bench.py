@@ -254,7 +254,81 @@ def extras(torch, mont, wl, dev):
     out["pow_n2^24"] = {"ms": round(s * 1e3, 4), "pow_per_s": round(e.size / s, 1),
                         "Gmodmul_per_s_algorithmic": round(alg / s / 1e9, 2),
                         "Gredc_per_s_executed": round(executed / s / 1e9, 2)}
+    del dbase, dexp, dout
+    out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
     return out
+
+
+def polymul_redc_count(da, db):
+    """Algorithmic REDC count of one product: three transforms of N/2 log2 N
+    butterflies, N pointwise products and db+1 operand scalings."""
+    need = da + db + 1
+    n = (int(need) - 1).bit_length()
+    N = 1 << n
+    return 3 * (N // 2) * n + N + db + 1
+
+
+def polymul_batch_extra(torch, wl, dev):
+    """2048 products, degrees log-uniform in [2^8, 2^20), 8 primes: one
+    persistent launch (eager and graph-replayed) against per-product plain
+    launches, all on the same inputs."""
+    from paper_1609_00999_amd import ntt
+    import oracle
+    batch = wl.polymul_batch()
+    ctx = ntt.Context(wl.PRIMES_NTT, 23)
+    plan = ntt.Plan.from_batch(ctx, batch)
+    din = torch.from_numpy(batch.coeffs.view(np.int32)).to(dev)
+    dout = torch.empty(batch.out_len, dtype=torch.int32, device=dev)
+    scr = plan.alloc_scratch()
+    redc = sum(polymul_redc_count(int(a), int(b)) for a, b in zip(batch.da, batch.db))
+    t_batch = timed(torch, lambda: plan.execute(din, dout, scr), 5)
+    st = plan.status(scr)
+    got = dout.cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(5)
+    bad = 0
+    for i in rng.choice(batch.count, 64, replace=False).tolist():
+        P, a, b = batch.operands(i)
+        c = got[batch.c_off[i]: batch.c_off[i] + a.size + b.size - 1]
+        x = int(rng.integers(2, P))
+        bad += oracle.horner(P, c, x) != oracle.horner(P, a, x) * oracle.horner(P, b, x) % P
+    # graph capture of the whole batch (fill kernel + persistent launch)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.execute(din, dout, scr)
+    torch.cuda.current_stream().wait_stream(s)
+    with torch.cuda.graph(g):
+        plan.execute(din, dout, scr)
+    t_graph = timed(torch, g.replay, 5)
+    # per-product plain launches
+    big = max(ntt.scratch_bytes(int(a), int(b)) for a, b in zip(batch.da, batch.db))
+    pscr = torch.empty(max(1, big // 4), dtype=torch.int32, device=dev)
+    views = []
+    for i in range(batch.count):
+        views.append((int(batch.prime_id[i]),
+                      din[batch.a_off[i]: batch.a_off[i] + batch.da[i] + 1],
+                      din[batch.b_off[i]: batch.b_off[i] + batch.db[i] + 1],
+                      dout[batch.c_off[i]: batch.c_off[i] + batch.da[i] + batch.db[i] + 1]))
+
+    def plain():
+        for pid, a, b, c in views:
+            ntt.polymul(ctx, pid, a, b, out=c, scratch=pscr)
+    t_plain = timed(torch, plain, 2)
+    res = {"products": batch.count, "status": st, "spot_check_failures": int(bad),
+           "persistent_ms": round(t_batch * 1e3, 3), "graph_ms": round(t_graph * 1e3, 3),
+           "plain_launches_ms": round(t_plain * 1e3, 3),
+           "polymul_per_s": round(batch.count / t_batch, 1),
+           "polymul_per_s_graph": round(batch.count / t_graph, 1),
+           "polymul_per_s_plain": round(batch.count / t_plain, 1),
+           "speedup_vs_plain": round(t_plain / t_batch, 2),
+           "Gredc_per_s": round(redc / t_batch / 1e9, 2), "redc_per_batch": int(redc),
+           "tasks": plan.ntasks, "grid": plan.default_grid}
+    log("polymul batch: %s" % res)
+    del g
+    plan.close()
+    ctx.close()
+    return res
 
 
 if __name__ == "__main__":

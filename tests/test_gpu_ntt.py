@@ -287,3 +287,38 @@ def test_batch_config_full_size(N, ctx):
     jobs = [batch.operands(i) for i in sample]
     for i, ref in zip(sample, oracle.polymul_many(jobs)):
         assert np.array_equal(got[batch.c_off[i]: batch.c_off[i] + ref.size], ref), i
+
+
+def test_batch_graph_replay(N, ctx):
+    """The batch captured in a graph (fill kernel + persistent launch) gives the
+    eager result on every replay, with eager work and synchronizations in
+    between."""
+    batch = small_batch(48, 6, 18, 44)
+    ref = oracle_batch(batch)
+    plan = N.Plan.from_batch(ctx, batch)
+    din = dev(batch.coeffs)
+    out = torch.zeros(batch.out_len, dtype=torch.int32, device="cuda")
+    scr = plan.alloc_scratch()
+    plan.execute(din, out, scr)
+    assert plan.status(scr) == 0
+    eager = host(out)
+    assert np.array_equal(eager, ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.execute(din, out, scr)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.execute(din, out, scr)
+    for r in range(4):
+        out.zero_()
+        scr.fill_(-1)                      # eager work that dirties the scratch header
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert plan.status(scr) == 0, r
+        assert np.array_equal(host(out), eager), r
+    del g
+    plan.close()
