@@ -77,56 +77,128 @@ __device__ __forceinline__ Mod mod_of(const PrimeDev& pr) { return Mod{pr.P, pr.
 // LDS stages.  X is viewed as rows x C columns (C = 2^lc, element (k, c) at
 // X[k*C + c]); the transform runs along rows, independently per column.  The
 // global index of element (k, c) is colbase + c + k*S with S = 2^rs, so the
-// stage with row half-distance h' = 2^s has global half-size h = h' S and
-// twiddle index h + (i mod h) = (h' << rs) + colbase + c + ((k mod h') << rs).
-// NA arrays at X and X + off are transformed together (one barrier per stage).
+// stage with row half-distance 2^s has global half-size h = 2^(s+rs) and
+// twiddle index h + (i mod h) = 2^(s+rs) + colbase + c + ((k mod 2^s) << rs).
+//
+// Stages are done R at a time in registers (a radix-2^R round): a lane loads
+// the 2^R residues whose rows differ only in bits s_lo .. s_lo+R-1, applies
+// the R radix-2 stages to them, and stores them back, so LDS is read and
+// written once per round instead of once per stage, and one barrier ends the
+// round.  Inside a group the twiddle of stage s_lo+t depends only on the low
+// t bits of the element's position in the group, so a round loads 2^R - 1
+// twiddles per group instead of R 2^(R-1).
 // ---------------------------------------------------------------------------
 
-template <int NT, int NA>
-__device__ void lds_dif(uint32_t* X, int off, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw,
-                        Mod md) {
-  const int nb = 1 << (lr - 1 + lc);
-  const uint32_t cmask = (1u << lc) - 1;
-  for (int s = lr - 1; s >= 0; s--) {
-    const uint32_t hmask = (1u << s) - 1;
-    for (int b = threadIdx.x; b < nb; b += NT) {
-      const uint32_t c = b & cmask;
-      const uint32_t q = (uint32_t)b >> lc;
-      const uint32_t k = ((q >> s) << (s + 1)) | (q & hmask);
-      const uint32_t i1 = (k << lc) | c;
-      const uint32_t i2 = i1 + (1u << (s + lc));
-      const uint32_t w = tw[(1u << (s + rs)) + colbase + c + ((q & hmask) << rs)];
+constexpr int kRadixLog = 4;           // at most 4 stages per LDS round
+
+// Twiddle tables are reached through pointers stored in device memory, so the
+// compiler cannot tell their address space; reading them as global memory
+// keeps the loads off the FLAT path (whose counter is shared with LDS).
+typedef const __attribute__((address_space(1))) uint32_t* gptr_u32;
+__device__ __forceinline__ uint32_t ldg(const uint32_t* p, uint32_t i) {
+  return ((gptr_u32)p)[i];
+}
+
+template <int NT, int NA, int R, bool INV>
+__device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int s_lo, int lc, int rs,
+                                          uint32_t colbase, const uint32_t* tw, Mod md) {
+  constexpr int E = 1 << R;
+  const int a_lo = s_lo + lc;                      // LDS address bit of stage s_lo
+  const uint32_t lomask = (1u << a_lo) - 1;
+  const uint32_t ngroups = M >> R;
+  for (uint32_t g = threadIdx.x; g < ngroups; g += NT) {
+    const uint32_t base = ((g & ~lomask) << R) | (g & lomask);   // zero in bits a_lo .. a_lo+R-1
+    const uint32_t c = base & ((1u << lc) - 1);
+    const uint32_t kb = base >> lc;
+    const uint32_t t0 = colbase + c + ((kb & ((1u << s_lo) - 1)) << rs);
+    uint32_t w[E - 1];
 #pragma unroll
-      for (int a = 0; a < NA; a++) {
-        uint32_t* Y = X + a * off;
-        const uint32_t u = Y[i1], v = Y[i2];
-        Y[i1] = madd(u, v, md.P);
-        Y[i2] = mmul(msub(u, v, md.P), w, md);
+    for (int t = 0; t < R; t++)
+#pragma unroll
+      for (int jj = 0; jj < (1 << t); jj++)
+        w[(1 << t) - 1 + jj] = ldg(tw, (1u << (s_lo + t + rs)) + t0 + ((uint32_t)jj << (s_lo + rs)));
+#pragma nounroll
+    for (int a = 0; a < NA; a++) {
+      uint32_t* Y = X + a * off + base;
+      uint32_t v[E];
+#pragma unroll
+      for (int j = 0; j < E; j++) v[j] = Y[(uint32_t)j << a_lo];
+      if constexpr (!INV) {
+#pragma unroll
+        for (int t = R - 1; t >= 0; t--) {
+          const int d = 1 << t;
+#pragma unroll
+          for (int j = 0; j < E; j++) {
+            if (j & d) continue;
+            const uint32_t x = v[j], y = v[j + d];
+            v[j] = madd(x, y, md.P);
+            v[j + d] = mmul(msub(x, y, md.P), w[d - 1 + (j & (d - 1))], md);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < R; t++) {
+          const int d = 1 << t;
+#pragma unroll
+          for (int j = 0; j < E; j++) {
+            if (j & d) continue;
+            const uint32_t x = v[j];
+            const uint32_t y = mmul(v[j + d], w[d - 1 + (j & (d - 1))], md);
+            v[j] = madd(x, y, md.P);
+            v[j + d] = msub(x, y, md.P);
+          }
+        }
       }
+#pragma unroll
+      for (int j = 0; j < E; j++) Y[(uint32_t)j << a_lo] = v[j];
     }
-    __syncthreads();
+  }
+  __syncthreads();
+}
+
+template <int NT, int NA, bool INV>
+__device__ __forceinline__ void lds_round_r(int r, uint32_t* X, int off, uint32_t M, int s_lo, int lc, int rs,
+                                            uint32_t colbase, const uint32_t* tw, Mod md) {
+  switch (r) {
+    case 1: lds_round<NT, NA, 1, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md); break;
+    case 2: lds_round<NT, NA, 2, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md); break;
+    case 3: lds_round<NT, NA, 3, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md); break;
+    default:
+      if constexpr (kRadixLog >= 4) lds_round<NT, NA, 4, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md);
+      break;
   }
 }
 
+// Round sizes for lr stages: ceil(lr / kRadixLog) rounds, as even as
+// possible, the larger ones first.
+__device__ __forceinline__ int round_size(int lr, int idx) {
+  const int nr = (lr + kRadixLog - 1) / kRadixLog;
+  const int base = lr / nr, extra = lr % nr;
+  return base + (idx < extra ? 1 : 0);
+}
+
+// Forward (decimation in frequency): stages lr-1 .. 0, rounds from the top.
+template <int NT, int NA>
+__device__ __forceinline__ void lds_dif(uint32_t* X, int off, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw,
+                        Mod md) {
+  const uint32_t M = 1u << (lr + lc);
+  int s_hi = lr;
+  for (int idx = 0; s_hi > 0; idx++) {
+    const int r = round_size(lr, idx);
+    s_hi -= r;
+    lds_round_r<NT, NA, false>(r, X, off, M, s_hi, lc, rs, colbase, tw, md);
+  }
+}
+
+// Inverse (decimation in time): stages 0 .. lr-1, rounds from the bottom.
 template <int NT>
-__device__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw, Mod md) {
-  const int nb = 1 << (lr - 1 + lc);
-  const uint32_t cmask = (1u << lc) - 1;
-  for (int s = 0; s < lr; s++) {
-    const uint32_t hmask = (1u << s) - 1;
-    for (int b = threadIdx.x; b < nb; b += NT) {
-      const uint32_t c = b & cmask;
-      const uint32_t q = (uint32_t)b >> lc;
-      const uint32_t k = ((q >> s) << (s + 1)) | (q & hmask);
-      const uint32_t i1 = (k << lc) | c;
-      const uint32_t i2 = i1 + (1u << (s + lc));
-      const uint32_t w = tw[(1u << (s + rs)) + colbase + c + ((q & hmask) << rs)];
-      const uint32_t u = X[i1];
-      const uint32_t v = mmul(X[i2], w, md);
-      X[i1] = madd(u, v, md.P);
-      X[i2] = msub(u, v, md.P);
-    }
-    __syncthreads();
+__device__ __forceinline__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw, Mod md) {
+  const uint32_t M = 1u << (lr + lc);
+  int s_lo = 0;
+  for (int idx = 0; s_lo < lr; idx++) {
+    const int r = round_size(lr, idx);
+    lds_round_r<NT, 1, true>(r, X, 0, M, s_lo, lc, rs, colbase, tw, md);
+    s_lo += r;
   }
 }
 
@@ -139,7 +211,7 @@ __device__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uint32_t colbase, c
 // load, forward transforms of both, pointwise REDC (which removes one R and
 // leaves a b / N), inverse transform, store of the da + db + 1 coefficients.
 template <int NT>
-__device__ void exec_small_poly(const PrimeDev& pr, int n, const uint32_t* a, uint32_t da, const uint32_t* b,
+__device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const uint32_t* a, uint32_t da, const uint32_t* b,
                                 uint32_t db, uint32_t* out, uint32_t* X) {
   const Mod md = mod_of(pr);
   const uint32_t N = 1u << n;
@@ -163,7 +235,7 @@ __device__ void exec_small_poly(const PrimeDev& pr, int n, const uint32_t* a, ui
 // Forward column pass, tile t: rows k < 2^n1, columns t*C + c; the input is
 // zero beyond index dvalid; scale != 0 multiplies by REDC(x * scale) on load.
 template <int NT>
-__device__ void exec_col_dif(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t dvalid,
+__device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t dvalid,
                              uint32_t scale, uint32_t* dst, uint32_t* X) {
   const Mod md = mod_of(pr);
   const int n1 = n - kRowLog;
@@ -188,7 +260,7 @@ __device__ void exec_col_dif(const PrimeDev& pr, int n, int lc, uint32_t t, cons
 // Inverse column pass, tile t: the last n1 inverse stages; stores only
 // indices < nout.
 template <int NT>
-__device__ void exec_col_dit(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t* dst,
+__device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t* dst,
                              uint32_t nout, uint32_t* X) {
   const Mod md = mod_of(pr);
   const int n1 = n - kRowLog;
@@ -216,7 +288,7 @@ enum RowMode { ROW_POLY = 0, ROW_FWD = 1, ROW_INV = 2 };
 //   ROW_FWD:  forward stages on A;
 //   ROW_INV:  A scaled by REDC(x * prescale) on load, inverse stages on A.
 template <int NT>
-__device__ void exec_row(const PrimeDev& pr, int lr, int mode, uint32_t* gA, const uint32_t* gB,
+__device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, uint32_t* gA, const uint32_t* gB,
                          uint32_t prescale, uint32_t* X) {
   const Mod md = mod_of(pr);
   const uint32_t L = 1u << lr;
@@ -275,7 +347,7 @@ enum DirectKind : uint32_t {
 };
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_ntt_direct(DirectArgs g) {
+__global__ __launch_bounds__(NT, 4) void k_ntt_direct(DirectArgs g) {
   __shared__ uint32_t X[kLdsWords];
   const PrimeDev& pr = g.primes[g.prime_id];
   const uint32_t bid = blockIdx.x;
@@ -315,9 +387,13 @@ struct PlanArgs {
   uint32_t spin_limit;
 };
 
+// Spin (lane 0 only) until *ctr >= need.  The loop reads the counter with
+// relaxed agent-scope loads, which go past the non-coherent caches without
+// invalidating them; one acquire fence after success makes the producers'
+// data visible (it invalidates this CU's L1 and this XCD's L2 once).
 __device__ __forceinline__ bool wait_count(uint32_t* ctr, uint32_t need, uint32_t* status, uint32_t spin_limit) {
   uint32_t it = 0;
-  while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
     if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     if (++it > spin_limit) {
       __hip_atomic_store(status, kStatusTimeout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -325,11 +401,17 @@ __device__ __forceinline__ bool wait_count(uint32_t* ctr, uint32_t need, uint32_
     }
     __builtin_amdgcn_s_sleep(4);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
+// s_waitcnt with vmcnt = 0 and the other counters at their maximum (gfx9
+// encoding: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8], vmcnt_hi[15:14]): the
+// wave's outstanding global stores have been acknowledged by L2.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 template <int NT>
-__global__ __launch_bounds__(NT) void k_ntt_persistent(PlanArgs g) {
+__global__ __launch_bounds__(NT, 4) void k_ntt_persistent(PlanArgs g) {
   __shared__ uint32_t X[kLdsWords];
   __shared__ uint32_t s_task, s_go;
   uint32_t* head = g.scr;
@@ -357,7 +439,6 @@ __global__ __launch_bounds__(NT) void k_ntt_persistent(PlanArgs g) {
       s_go = go ? 1u : 0u;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (s_go) {
       switch (kind) {
         case T_SMALL:
@@ -371,12 +452,17 @@ __global__ __launch_bounds__(NT) void k_ntt_persistent(PlanArgs g) {
         default: exec_col_dit<NT>(pr, pd.n, pd.lc, idx, scr, g.out + pd.c_off, pd.da + pd.db + 1, X); break;
       }
       if (kind != T_SMALL && kind != T_COLI) {
-        // Publish this task's stores at agent scope before counting it.
-        __threadfence();
+        // Publish this task's stores at agent scope before counting it: every
+        // wave waits until its stores are in L2, then one lane writes the L2
+        // back (the release fence) so other XCDs can read the data, and only
+        // then bumps the product's counter.
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
         if (threadIdx.x == 0) {
           uint32_t* ctr = kind == T_ROW ? cnt_row + p : cnt_col + p;
-          __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);      // the write-back has completed
+          __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
