@@ -256,7 +256,65 @@ def extras(torch, mont, wl, dev):
                         "Gredc_per_s_executed": round(executed / s / 1e9, 2)}
     del dbase, dexp, dout
     out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
+    out["serving"] = serving_extra(torch, wl, dev)
     return out
+
+
+# Poisson arrival rate of the serving workload, calibrated once to about 70 %
+# of the batched executor's saturated throughput on MI355X, then frozen.
+SERVE_RATE = 20000.0
+SERVE_REQUESTS = 10000
+SERVE_WARMUP = 1000
+
+
+def serving_extra(torch, wl, dev, count=SERVE_REQUESTS + SERVE_WARMUP, rate=SERVE_RATE, warmup=SERVE_WARMUP):
+    """Poisson stream of elementwise (n log-uniform 2^10..2^24) and polynomial
+    (degree log-uniform 2^10..2^22) requests over the 8 primes: continuous
+    batching on 4 slots against per-request plain launches, same arrivals."""
+    from paper_1609_00999_amd import ntt, serve
+    import oracle
+    reqs = wl.request_stream(count, rate)
+    t0 = time.time()
+    inputs = serve.DeviceInputs(reqs, wl.PRIMES_NTT)
+    log("serving inputs resident (%.1f s, %.2f GB)" % (time.time() - t0, inputs.arena.numel() * 4 / 1e9))
+    ctx = ntt.Context(wl.PRIMES_NTT, 23)
+    rng = np.random.default_rng(55)
+    sample = rng.choice(count, 64, replace=False).tolist()
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=4, max_batch=64, keep_results=set(sample))
+    budget = 48 << 30
+    stats = serve.Scheduler(ex, slots=4, budget_bytes=budget, max_batch=64).run(serve.jobs_from_requests(reqs))
+    res = {"rate_req_per_s": rate, "requests": count - warmup, "warmup": warmup, "slots": 4,
+           "budget_bytes": budget, "batched": stats.summary(warmup)}
+    # exactness: a seeded sample of requests against the oracle (full product
+    # for short polynomials, Schwartz-Zippel at two points for long ones)
+    bad = 0
+    byid = {j.rid: j for j in stats.jobs}
+    for rid in sample:
+        j, r = byid[rid], reqs[rid]
+        P = wl.PRIMES_NTT[r.prime_id]
+        a, b = inputs.host_operands(rid)
+        got = j.result.cpu().numpy().view(np.uint32)
+        if r.kind == "mul":
+            bad += not np.array_equal(got, oracle.mont_mul(P, a, b))
+        elif r.size <= 4096:
+            bad += not np.array_equal(got, oracle.polymul(P, a, b))
+        else:
+            for x in rng.integers(2, P, 2).tolist():
+                bad += oracle.horner(P, got, x) != oracle.horner(P, a, x) * oracle.horner(P, b, x) % P
+    res["sample_checked"] = len(sample)
+    res["sample_failures"] = int(bad)
+    for j in stats.jobs:
+        j.result = None
+    ex.close()
+    plain = serve.GpuPlainExecutor(ctx, inputs, keep_results=False)
+    pst = serve.Scheduler(plain, slots=1, budget_bytes=budget, max_batch=1).run(serve.jobs_from_requests(reqs))
+    res["plain_launches"] = pst.summary(warmup)
+    b, p = res["batched"], res["plain_launches"]
+    if b.get("p99_ms") and p.get("p99_ms"):
+        res["p99_speedup_vs_plain"] = round(p["p99_ms"] / b["p99_ms"], 2)
+    log("serving: %s" % res)
+    ctx.close()
+    return res
 
 
 def polymul_redc_count(da, db):

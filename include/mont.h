@@ -116,6 +116,45 @@ MONT_API mont_status mont_pow(const mont_params* prm, const uint32_t* d_base, co
                      size_t n, void* stream);
 
 /*
+ * Batches of vectors.  One descriptor per vector: device pointers a, b, out
+ * (n residues each, out may equal a or b), and the vector's own modulus P
+ * with P' = -P^-1 mod 2^32 as mont_setup returns them.
+ */
+typedef struct mont_vec_desc {
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t* out;
+  uint64_t n;
+  uint32_t P, Pprime;
+} mont_vec_desc;
+
+typedef struct mont_batch mont_batch;
+
+/* mont_batch_reserve -- a reusable batch object for up to max_vectors
+ * vectors (device descriptor array plus pinned staging). */
+MONT_API mont_status mont_batch_reserve(int max_vectors, mont_batch** out);
+
+/*
+ * mont_batch_update -- loads `count` host descriptors and uploads them
+ * asynchronously on `stream` (launches that use them go on the same stream,
+ * after this call).  Blocks only until the previous upload has left the
+ * staging buffer.  Errors: MONT_EINVAL (bad modulus pair, NULL pointer with
+ * n > 0), MONT_ERANGE (count above the reserved capacity), MONT_EHIP.
+ */
+MONT_API mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* descs, int count, void* stream);
+
+/*
+ * mont_batch_mul -- Algorithm 2 elementwise over every vector of the batch in
+ * ONE persistent launch: out_i[j] = REDC(a_i[j] * b_i[j]) modulo P_i.  The
+ * work is cut into tiles of 4096 residues that never straddle two vectors.
+ * Operands are residues in [0, P_i).
+ */
+MONT_API mont_status mont_batch_mul(const mont_batch* b, void* stream);
+
+/* Frees the batch object (synchronizes the device first). */
+MONT_API mont_status mont_batch_destroy(mont_batch* b);
+
+/*
  * Launch-shape tuning of the streaming elementwise kernels (used by the
  * autotuner).  op: 0 = to, 1 = from, 2 = mul, 3 = muladd, 4 = pow.  block is
  * 256 or 512 threads, vpt 1, 2 or 4 128-bit vectors per thread, nontemporal

@@ -115,6 +115,28 @@ typedef struct ntt_plan ntt_plan;
 MONT_API mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
                                      ntt_plan** out);
 
+/*
+ * ntt_plan_reserve -- a reusable plan with room for max_products products and
+ * max_tasks tasks (device arrays plus pinned host staging), for callers that
+ * plan a new batch often (a serving loop).  It holds no batch until
+ * ntt_plan_update.  ntt_plan_task_count(da, db) gives the tasks one product
+ * adds.  Errors: MONT_EINVAL, MONT_ENOMEM.
+ */
+MONT_API mont_status ntt_plan_reserve(const ntt_ctx* ctx, int max_products, uint32_t max_tasks, ntt_plan** out);
+MONT_API uint32_t ntt_plan_task_count(uint32_t da, uint32_t db);
+
+/*
+ * ntt_plan_update -- replans a reserved plan for a new batch (same rules and
+ * task order as ntt_plan_create) and uploads it asynchronously on `stream`;
+ * executions of the plan must be enqueued on the same stream, after this
+ * call, so that they see the new lists.  Blocks only until the previous
+ * update's upload has left the staging buffers.  Errors: MONT_EINVAL (not a
+ * reserved plan, bad descriptor), MONT_ERANGE (beyond the reserved capacity,
+ * or a product too long), MONT_ENOROOT, MONT_EHIP.
+ */
+MONT_API mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs, int count, uint32_t order_seed,
+                                     void* stream);
+
 /* Sizes a caller needs: scratch bytes, task count, the minimum lengths (in
  * words) of d_in and d_out, and the default persistent grid (resident
  * workgroups on the device).  Any output pointer may be NULL. */

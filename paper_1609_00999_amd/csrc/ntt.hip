@@ -593,6 +593,15 @@ struct ntt_plan {
   ProdDev* d_prods = nullptr;
   uint2* d_tasks = nullptr;
   int default_grid = 0;
+  // Reusable plans (ntt_plan_reserve): device capacity and pinned staging
+  // for asynchronous updates; `staged` marks the last upload from staging.
+  bool reusable = false;
+  int cap_prods = 0;
+  uint32_t cap_tasks = 0;
+  ProdDev* h_prods = nullptr;
+  uint2* h_tasks = nullptr;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
 };
 
 namespace {
@@ -813,18 +822,24 @@ extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint3
 // Batch plans.
 // ---------------------------------------------------------------------------
 
-extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
-                                       ntt_plan** out) {
-  if (!ctx || !out || count < 0 || (count > 0 && !descs)) return MONT_EINVAL;
-  *out = nullptr;
-  std::vector<ProdDev> prods(count);
+namespace {
+
+// Host side of planning: per-product descriptors, the ordered task list and
+// the scratch layout (header, two counters per product, then 2N words per
+// multi-pass product).
+mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
+                       std::vector<ProdDev>& prods, std::vector<uint2>& tasks, uint64_t& scr_words,
+                       uint64_t& in_words, uint64_t& out_words) {
+  prods.assign(count, ProdDev{});
+  tasks.clear();
   std::vector<uint2> colf, small, row, coli;
   uint64_t scr = kHdrWords + 2ull * count;
   scr = (scr + 63) & ~63ull;
-  uint64_t in_words = 0, out_words = 0;
+  in_words = 0;
+  out_words = 0;
   for (int p = 0; p < count; p++) {
     const polymul_desc& d = descs[p];
-    if (d.prime_id >= ctx->params.size()) return MONT_EINVAL;
+    if (d.prime_id >= ctx->params.size() || d.reserved != 0) return MONT_EINVAL;
     uint64_t nout = (uint64_t)d.da + d.db + 1;
     if (nout > ((uint64_t)1 << 31)) return MONT_ERANGE;
     int n = ceil_log2(nout);
@@ -871,7 +886,6 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
     std::shuffle(row.begin(), row.end(), rng);
     std::shuffle(coli.begin(), coli.end(), rng);
   }
-  std::vector<uint2> tasks;
   tasks.reserve(colf.size() + small.size() + row.size() + coli.size());
   size_t half = small.size() / 2;
   tasks.insert(tasks.end(), colf.begin(), colf.end());
@@ -879,7 +893,40 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
   tasks.insert(tasks.end(), row.begin(), row.end());
   tasks.insert(tasks.end(), small.begin() + half, small.end());
   tasks.insert(tasks.end(), coli.begin(), coli.end());
+  scr_words = scr;
+  return MONT_OK;
+}
 
+int persistent_grid() {
+  int dev = 0, cus = 256, per_cu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ntt_persistent<kThreads>, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return cus * per_cu;
+}
+
+void free_plan(ntt_plan* plan) {
+  (void)hipFree(plan->d_prods);
+  (void)hipFree(plan->d_tasks);
+  if (plan->h_prods) (void)hipHostFree(plan->h_prods);
+  if (plan->h_tasks) (void)hipHostFree(plan->h_tasks);
+  if (plan->staged) (void)hipEventDestroy(plan->staged);
+  delete plan;
+}
+
+}  // namespace
+
+extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
+                                       ntt_plan** out) {
+  if (!ctx || !out || count < 0 || (count > 0 && !descs)) return MONT_EINVAL;
+  *out = nullptr;
+  std::vector<ProdDev> prods;
+  std::vector<uint2> tasks;
+  uint64_t scr = 0, in_words = 0, out_words = 0;
+  mont_status st = build_plan(ctx, descs, count, order_seed, prods, tasks, scr, in_words, out_words);
+  if (st != MONT_OK) return st;
   ntt_plan* plan = new (std::nothrow) ntt_plan;
   if (!plan) return MONT_ENOMEM;
   plan->ctx = ctx;
@@ -891,28 +938,81 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
   if (count > 0) {
     if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * count) != hipSuccess ||
         hipMalloc(&plan->d_tasks, sizeof(uint2) * std::max<size_t>(1, tasks.size())) != hipSuccess) {
-      (void)hipFree(plan->d_prods);
-      delete plan;
+      free_plan(plan);
       return MONT_ENOMEM;
     }
     if (hipMemcpy(plan->d_prods, prods.data(), sizeof(ProdDev) * count, hipMemcpyHostToDevice) != hipSuccess ||
         (tasks.size() && hipMemcpy(plan->d_tasks, tasks.data(), sizeof(uint2) * tasks.size(),
                                    hipMemcpyHostToDevice) != hipSuccess)) {
-      (void)hipFree(plan->d_prods);
-      (void)hipFree(plan->d_tasks);
-      delete plan;
+      free_plan(plan);
       return MONT_EHIP;
     }
   }
-  int dev = 0, cus = 256, per_cu = 1;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ntt_persistent<kThreads>, kThreads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  plan->default_grid = cus * per_cu;
+  plan->default_grid = persistent_grid();
   *out = plan;
   return MONT_OK;
+}
+
+extern "C" mont_status ntt_plan_reserve(const ntt_ctx* ctx, int max_products, uint32_t max_tasks, ntt_plan** out) {
+  if (!ctx || !out || max_products < 1 || max_tasks < 1) return MONT_EINVAL;
+  *out = nullptr;
+  ntt_plan* plan = new (std::nothrow) ntt_plan;
+  if (!plan) return MONT_ENOMEM;
+  plan->ctx = ctx;
+  plan->reusable = true;
+  plan->cap_prods = max_products;
+  plan->cap_tasks = max_tasks;
+  if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * max_products) != hipSuccess ||
+      hipMalloc(&plan->d_tasks, sizeof(uint2) * max_tasks) != hipSuccess ||
+      hipHostMalloc((void**)&plan->h_prods, sizeof(ProdDev) * max_products, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&plan->h_tasks, sizeof(uint2) * max_tasks, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming) != hipSuccess) {
+    free_plan(plan);
+    return MONT_ENOMEM;
+  }
+  plan->default_grid = persistent_grid();
+  *out = plan;
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs, int count, uint32_t order_seed,
+                                       void* stream) {
+  if (!plan || !plan->reusable || count < 0 || (count > 0 && !descs)) return MONT_EINVAL;
+  if (count > plan->cap_prods) return MONT_ERANGE;
+  std::vector<ProdDev> prods;
+  std::vector<uint2> tasks;
+  uint64_t scr = 0, in_words = 0, out_words = 0;
+  mont_status st = build_plan(plan->ctx, descs, count, order_seed, prods, tasks, scr, in_words, out_words);
+  if (st != MONT_OK) return st;
+  if (tasks.size() > plan->cap_tasks) return MONT_ERANGE;
+  // The previous upload must have finished reading the staging buffers.
+  if (plan->staged_pending && hipEventSynchronize(plan->staged) != hipSuccess) return MONT_EHIP;
+  plan->staged_pending = false;
+  hipStream_t s = as_stream(stream);
+  if (count > 0) {
+    std::memcpy(plan->h_prods, prods.data(), sizeof(ProdDev) * count);
+    if (!tasks.empty()) std::memcpy(plan->h_tasks, tasks.data(), sizeof(uint2) * tasks.size());
+    if (hipMemcpyAsync(plan->d_prods, plan->h_prods, sizeof(ProdDev) * count, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        (!tasks.empty() && hipMemcpyAsync(plan->d_tasks, plan->h_tasks, sizeof(uint2) * tasks.size(),
+                                          hipMemcpyHostToDevice, s) != hipSuccess) ||
+        hipEventRecord(plan->staged, s) != hipSuccess)
+      return MONT_EHIP;
+    plan->staged_pending = true;
+  }
+  plan->count = count;
+  plan->ntasks = (uint32_t)tasks.size();
+  plan->scratch_words = scr;
+  plan->in_words = in_words;
+  plan->out_words = out_words;
+  return MONT_OK;
+}
+
+extern "C" uint32_t ntt_plan_task_count(uint32_t da, uint32_t db) {
+  int n = ceil_log2((uint64_t)da + db + 1);
+  if (n <= kRowLog) return 1;
+  uint32_t ntiles = 1u << (kRowLog - col_lc(n));
+  return 3 * ntiles + (1u << (n - kRowLog));
 }
 
 extern "C" mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, uint32_t* ntasks,
@@ -968,8 +1068,6 @@ extern "C" mont_status ntt_plan_status(const ntt_plan* plan, const void* d_scrat
 extern "C" mont_status ntt_plan_destroy(ntt_plan* plan) {
   if (!plan) return MONT_EINVAL;
   (void)hipDeviceSynchronize();
-  (void)hipFree(plan->d_prods);
-  (void)hipFree(plan->d_tasks);
-  delete plan;
+  free_plan(plan);
   return MONT_OK;
 }

@@ -53,6 +53,10 @@ def lib() -> ctypes.CDLL:
     for name in ("mont_mul", "mont_pow"):
         getattr(L, name).argtypes = [pp, c_vp, c_vp, c_vp, c_size, c_vp]
     L.mont_muladd.argtypes = [pp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]
+    L.mont_batch_reserve.argtypes = [ctypes.c_int, ctypes.POINTER(c_vp)]
+    L.mont_batch_update.argtypes = [c_vp, c_vp, ctypes.c_int, c_vp]
+    L.mont_batch_mul.argtypes = [c_vp, c_vp]
+    L.mont_batch_destroy.argtypes = [c_vp]
     L.mont_elem_tune_set.argtypes = [ctypes.c_int] * 4
     L.mont_elem_tune_get.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
     _register_ntt(L)
@@ -174,6 +178,50 @@ def pow(prm: MontParams, base, exp, out=None):  # noqa: A001 - mirrors mont_pow
     check(lib().mont_pow(ctypes.byref(prm), dev_ptr(base, "base"), dev_ptr(exp, "exp"), dev_ptr(out, "out"),
                          base.numel(), stream_handle()), "mont_pow")
     return out
+
+
+class VecDesc(ctypes.Structure):
+    """Mirror of ``mont_vec_desc`` (include/mont.h)."""
+    _fields_ = [("a", c_vp), ("b", c_vp), ("out", c_vp), ("n", ctypes.c_uint64), ("P", c_u32), ("Pprime", c_u32)]
+
+
+class Batch:
+    """Reusable batch of vectors, each with its own modulus (mont_batch)."""
+
+    def __init__(self, max_vectors: int):
+        h = c_vp()
+        check(lib().mont_batch_reserve(max_vectors, ctypes.byref(h)), "mont_batch_reserve")
+        self.handle = h
+        self.cap = max_vectors
+        self._keep = None
+
+    def close(self):
+        if self.handle:
+            check(lib().mont_batch_destroy(self.handle), "mont_batch_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, items):
+        """items: list of (prm, a, b, out) with device tensors of equal length."""
+        arr = (VecDesc * max(1, len(items)))()
+        for i, (prm, a, b, out) in enumerate(items):
+            if not (a.numel() == b.numel() == out.numel()):
+                raise ValueError("vector %d: sizes differ" % i)
+            arr[i] = VecDesc(dev_ptr(a, "a"), dev_ptr(b, "b"), dev_ptr(out, "out"), a.numel(), prm.P, prm.Pprime)
+        self._keep = items
+        check(lib().mont_batch_update(self.handle, arr, len(items), stream_handle()), "mont_batch_update")
+
+    def update_raw(self, descs):
+        """descs: a ctypes array of VecDesc (pointers already resolved)."""
+        check(lib().mont_batch_update(self.handle, descs, len(descs), stream_handle()), "mont_batch_update")
+
+    def mul(self):
+        check(lib().mont_batch_mul(self.handle, stream_handle()), "mont_batch_mul")
 
 
 ELEM_OPS = {"to": 0, "from": 1, "mul": 2, "muladd": 3, "pow": 4}

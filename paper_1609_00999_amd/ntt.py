@@ -44,6 +44,10 @@ def register(L) -> None:
     L.ntt_polymul_scratch_bytes.restype = c_size
     L.ntt_polymul.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp, c_u32, c_vp, c_vp, c_size, c_vp]
     L.ntt_plan_create.argtypes = [c_vp, c_vp, c_int, c_u32, vpp]
+    L.ntt_plan_reserve.argtypes = [c_vp, c_int, c_u32, vpp]
+    L.ntt_plan_task_count.argtypes = [c_u32, c_u32]
+    L.ntt_plan_task_count.restype = c_u32
+    L.ntt_plan_update.argtypes = [c_vp, c_vp, c_int, c_u32, c_vp]
     L.ntt_plan_info.argtypes = [c_vp, ctypes.POINTER(c_size), ctypes.POINTER(c_u32), ctypes.POINTER(c_u64),
                                 ctypes.POINTER(c_u64), ctypes.POINTER(c_int)]
     L.ntt_plan_execute.argtypes = [c_vp, c_vp, c_vp, c_vp, c_size, c_int, c_u32, c_vp]
@@ -149,28 +153,61 @@ def polymul(ctx: Context, prime_id: int, a, b, out=None, scratch=None):
     return out
 
 
+def task_count(da: int, db: int) -> int:
+    """Tasks one product adds to a plan."""
+    return int(mont.lib().ntt_plan_task_count(da, db))
+
+
+def make_descs(prime_id, da, db, a_off, b_off, c_off) -> np.ndarray:
+    count = len(da)
+    descs = np.zeros(count, dtype=DESC_DTYPE)
+    descs["prime_id"] = prime_id
+    descs["da"] = da
+    descs["db"] = db
+    descs["a_off"] = a_off
+    descs["b_off"] = b_off
+    descs["c_off"] = c_off
+    return descs
+
+
 class Plan:
     """A planned batch of polynomial products for one persistent launch (ntt_plan)."""
 
-    def __init__(self, ctx: Context, prime_id, da, db, a_off, b_off, c_off, order_seed: int = 0):
+    def __init__(self, ctx: Context, prime_id, da, db, a_off, b_off, c_off, order_seed: int = 0, _reserve=None):
         L = mont.lib()
-        count = len(da)
-        descs = np.zeros(count, dtype=DESC_DTYPE)
-        descs["prime_id"] = prime_id
-        descs["da"] = da
-        descs["db"] = db
-        descs["a_off"] = a_off
-        descs["b_off"] = b_off
-        descs["c_off"] = c_off
-        self._descs = descs
         h = c_vp()
+        self.ctx = ctx
+        if _reserve is not None:
+            max_products, max_tasks = _reserve
+            mont.check(L.ntt_plan_reserve(ctx.handle, max_products, max_tasks, ctypes.byref(h)), "ntt_plan_reserve")
+            self.handle = h
+            self._info()
+            return
+        descs = make_descs(prime_id, da, db, a_off, b_off, c_off)
+        count = len(descs)
+        self._descs = descs
         mont.check(L.ntt_plan_create(ctx.handle, descs.ctypes.data if count else None, count, order_seed,
                                      ctypes.byref(h)), "ntt_plan_create")
         self.handle = h
-        self.ctx = ctx
+        self._info()
+
+    @classmethod
+    def reserve(cls, ctx: Context, max_products: int, max_tasks: int):
+        """A reusable plan (ntt_plan_reserve); fill it with update()."""
+        return cls(ctx, None, None, None, None, None, None, _reserve=(max_products, max_tasks))
+
+    def update(self, descs: np.ndarray, order_seed: int = 0):
+        """Replan for a new batch (structured array of DESC_DTYPE), uploaded on the current stream."""
+        descs = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+        self._descs = descs
+        mont.check(mont.lib().ntt_plan_update(self.handle, descs.ctypes.data if len(descs) else None, len(descs),
+                                              order_seed, mont.stream_handle()), "ntt_plan_update")
+        self._info()
+
+    def _info(self):
         sb, nt, iw, ow, g = c_size(), c_u32(), c_u64(), c_u64(), c_int()
-        mont.check(L.ntt_plan_info(h, ctypes.byref(sb), ctypes.byref(nt), ctypes.byref(iw), ctypes.byref(ow),
-                                   ctypes.byref(g)), "ntt_plan_info")
+        mont.check(mont.lib().ntt_plan_info(self.handle, ctypes.byref(sb), ctypes.byref(nt), ctypes.byref(iw),
+                                            ctypes.byref(ow), ctypes.byref(g)), "ntt_plan_info")
         self.scratch_bytes, self.ntasks = sb.value, nt.value
         self.in_words, self.out_words, self.default_grid = iw.value, ow.value, g.value
 

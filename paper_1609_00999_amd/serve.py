@@ -1,0 +1,361 @@
+"""Continuous-batching request loop for Montgomery products and polynomial
+products on one GPU.
+
+Requests (elementwise Montgomery products of n residues, or polynomial
+products of degree d) arrive over time.  The scheduler keeps them in a FIFO,
+and whenever an execution slot (a HIP stream with its own reusable batch
+objects) is free it admits the longest prefix of the queue whose device
+footprint (outputs + transform scratch) fits the HBM budget next to what is
+already in flight, and launches it as ONE batch: one persistent launch for
+all its elementwise requests and one for all its polynomial products.
+Requests that arrive while other batches run are admitted as slots and
+memory free up, and batches on different slots overlap on the device.
+Per-prime constants and twiddle tables stay resident in one ntt.Context.
+
+The executor interface (launch / poll / finish) lets the same scheduler
+drive the GPU executor, a per-request plain-launch executor (the baseline)
+and test doubles.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+OK = 0
+REJECTED = 1        # larger than the whole HBM budget
+CANCELLED = 2
+TIMED_OUT = 3       # waited in the queue longer than the request's timeout
+FAILED = 4          # the executor reported an error for this request
+
+STATUS_NAMES = {OK: "ok", REJECTED: "rejected", CANCELLED: "cancelled", TIMED_OUT: "timed_out", FAILED: "failed"}
+
+
+@dataclass
+class Job:
+    """One request as the scheduler sees it."""
+    rid: int
+    t_arrival: float             # seconds after the start of the run
+    kind: str                    # "mul" or "polymul"
+    prime_id: int
+    size: int                    # n for "mul", degree d for "polymul"
+    footprint: int = 0           # device bytes the request holds while in flight
+    timeout: float = float("inf")
+    payload: object = None       # executor-specific operand handles
+    status: int = -1
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    result: object = None
+    error: str = ""
+    cancelled: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrival
+
+
+@dataclass
+class RunStats:
+    jobs: list
+    wall: float
+    batches: int
+    max_inflight_bytes: int
+    batch_sizes: list = field(default_factory=list)
+
+    def latencies(self, kind=None, warmup: int = 0):
+        return np.array([j.latency for j in self.jobs[warmup:] if j.status == OK and (kind is None or j.kind == kind)])
+
+    def summary(self, warmup: int = 0) -> dict:
+        lat = self.latencies(warmup=warmup)
+        done = [j for j in self.jobs[warmup:] if j.status == OK]
+        out = {"requests": len(self.jobs) - warmup, "completed": len(done), "batches": self.batches,
+               "wall_s": round(self.wall, 4), "max_inflight_bytes": int(self.max_inflight_bytes)}
+        if lat.size:
+            span = max(j.t_done for j in done) - min(j.t_arrival for j in done)
+            out.update({"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                        "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                        "throughput_req_per_s": round(len(done) / span, 1) if span > 0 else None})
+            for kind in ("mul", "polymul"):
+                lk = self.latencies(kind, warmup)
+                if lk.size:
+                    out["p50_ms_" + kind] = round(float(np.percentile(lk, 50)) * 1e3, 3)
+                    out["p99_ms_" + kind] = round(float(np.percentile(lk, 99)) * 1e3, 3)
+        if self.batch_sizes:
+            out["mean_batch"] = round(float(np.mean(self.batch_sizes)), 2)
+        counts = collections.Counter(STATUS_NAMES.get(j.status, "?") for j in self.jobs[warmup:])
+        out["status_counts"] = dict(counts)
+        return out
+
+
+class Scheduler:
+    """FIFO admission by footprint into free slots; one batch per slot."""
+
+    def __init__(self, executor, slots: int = 4, budget_bytes: int = 16 << 30, max_batch: int = 256,
+                 clock=time.perf_counter, idle_sleep: float = 0.0):
+        if slots < 1 or budget_bytes <= 0 or max_batch < 1:
+            raise ValueError("slots, budget and max_batch must be positive")
+        self.ex = executor
+        self.slots = slots
+        self.budget = budget_bytes
+        self.max_batch = max_batch
+        self.clock = clock
+        self.idle_sleep = idle_sleep
+
+    def run(self, jobs: list) -> RunStats:
+        jobs = sorted(jobs, key=lambda j: (j.t_arrival, j.rid))
+        for j in jobs:
+            if j.footprint <= 0:
+                j.footprint = self.ex.footprint(j)
+        pending: collections.deque = collections.deque()
+        inflight = {}
+        free = list(range(self.slots))[::-1]
+        used = 0
+        max_used = 0
+        batches = 0
+        sizes = []
+        nxt = 0
+        t0 = self.clock()
+        while nxt < len(jobs) or pending or inflight:
+            now = self.clock() - t0
+            progressed = False
+            while nxt < len(jobs) and jobs[nxt].t_arrival <= now:
+                pending.append(jobs[nxt])
+                nxt += 1
+                progressed = True
+            # completions
+            for slot in list(inflight):
+                handle, batch, fp = inflight[slot]
+                if self.ex.poll(handle):
+                    t_done = self.clock() - t0
+                    errors = self.ex.finish(handle)
+                    for j in batch:
+                        j.t_done = t_done
+                        if j.rid in errors:
+                            j.status, j.error = FAILED, errors[j.rid]
+                        else:
+                            j.status = OK
+                    used -= fp
+                    del inflight[slot]
+                    free.append(slot)
+                    progressed = True
+            # drop cancelled and expired requests from the head of the queue
+            now = self.clock() - t0
+            if pending:
+                keep = collections.deque()
+                for j in pending:
+                    if j.cancelled:
+                        j.status, j.t_done = CANCELLED, now
+                    elif now - j.t_arrival > j.timeout:
+                        j.status, j.t_done = TIMED_OUT, now
+                    else:
+                        keep.append(j)
+                pending = keep
+            # admission: longest queue prefix that fits, one batch per free slot
+            while free and pending:
+                batch, fp = [], 0
+                while pending and len(batch) < self.max_batch:
+                    j = pending[0]
+                    if j.footprint > self.budget:
+                        pending.popleft()
+                        j.status, j.t_done = REJECTED, self.clock() - t0
+                        j.error = "footprint %d exceeds the budget %d" % (j.footprint, self.budget)
+                        continue
+                    if used + fp + j.footprint > self.budget:
+                        break
+                    batch.append(pending.popleft())
+                    fp += j.footprint
+                if not batch:
+                    break
+                slot = free.pop()
+                t_admit = self.clock() - t0
+                for j in batch:
+                    j.t_admit = t_admit
+                handle = self.ex.launch(slot, batch)
+                inflight[slot] = (handle, batch, fp)
+                used += fp
+                max_used = max(max_used, used)
+                batches += 1
+                sizes.append(len(batch))
+                progressed = True
+            if not progressed and self.idle_sleep > 0:
+                time.sleep(self.idle_sleep)
+        return RunStats(jobs, self.clock() - t0, batches, max_used, sizes)
+
+
+# ---------------------------------------------------------------------------
+# GPU executors
+# ---------------------------------------------------------------------------
+
+def _keeps(keep, rid) -> bool:
+    """keep is True (keep every result), False, or a set of request ids."""
+    return keep is True or (keep is not False and rid in keep)
+
+
+class DeviceInputs:
+    """Client-side operands: every request's inputs generated on the device
+    from the request's own seed and packed into one arena (resident in HBM
+    before the run starts, as a client would hand them over)."""
+
+    def __init__(self, reqs, primes, device="cuda"):
+        import torch
+        self.torch = torch
+        offs = {}
+        pos = 0
+        for r in reqs:
+            n = r.size if r.kind == "mul" else r.size + 1
+            offs[r.rid] = (pos, pos + n, n)
+            pos += 2 * n
+            pos = (pos + 3) & ~3            # keep every operand 16-byte aligned
+        self.arena = torch.empty(max(4, pos), dtype=torch.int32, device=device)
+        self.offs = offs
+        self.primes = primes
+        gen = torch.Generator(device=device)
+        for r in reqs:
+            a0, b0, n = offs[r.rid]
+            P = primes[r.prime_id]
+            gen.manual_seed(int(r.seed) & ((1 << 63) - 1))
+            vals = torch.randint(0, P, (2, n), generator=gen, device=device, dtype=torch.int64)
+            self.arena[a0:a0 + n].copy_(vals[0].to(torch.int32))
+            self.arena[b0:b0 + n].copy_(vals[1].to(torch.int32))
+        torch.cuda.synchronize()
+
+    def views(self, rid):
+        a0, b0, n = self.offs[rid]
+        return self.arena[a0:a0 + n], self.arena[b0:b0 + n]
+
+    def host_operands(self, rid):
+        a, b = self.views(rid)
+        return a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32)
+
+
+class GpuBatchExecutor:
+    """Runs each admitted batch as one persistent launch for its elementwise
+    requests and one for its polynomial products, on the slot's stream."""
+
+    def __init__(self, ctx, inputs: DeviceInputs, slots: int, max_batch: int, keep_results: bool = True,
+                 max_tasks: int = 1 << 20):
+        import torch
+        from . import mont, ntt
+        self.torch, self.mont, self.ntt = torch, mont, ntt
+        self.ctx = ctx
+        self.inputs = inputs
+        self.keep = keep_results
+        self.params = [mont.setup(P) for P in ctx.primes]
+        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.vecb = [mont.Batch(max_batch) for _ in range(slots)]
+        self.plans = [ntt.Plan.reserve(ctx, max_batch, max_tasks) for _ in range(slots)]
+        self.max_tasks = max_tasks
+
+    def footprint(self, job: Job) -> int:
+        if job.kind == "mul":
+            return 4 * job.size
+        d = job.size
+        return 4 * (2 * d + 1) + self.ntt.scratch_bytes(d, d) + 8
+
+    def launch(self, slot: int, batch):
+        torch, mont, ntt = self.torch, self.mont, self.ntt
+        s = self.streams[slot]
+        muls = [j for j in batch if j.kind == "mul"]
+        polys = [j for j in batch if j.kind == "polymul"]
+        keep = []
+        with torch.cuda.stream(s):
+            if muls:
+                descs = (mont.VecDesc * len(muls))()
+                for i, j in enumerate(muls):
+                    a, b = self.inputs.views(j.rid)
+                    out = torch.empty(j.size, dtype=torch.int32, device=a.device)
+                    prm = self.params[j.prime_id]
+                    descs[i] = mont.VecDesc(a.data_ptr(), b.data_ptr(), out.data_ptr(), j.size, prm.P, prm.Pprime)
+                    j.result = out
+                    keep.append(out)
+                self.vecb[slot].update_raw(descs)
+                self.vecb[slot].mul()
+            if polys:
+                desc = np.zeros(len(polys), dtype=ntt.DESC_DTYPE)
+                cpos = 0
+                for i, j in enumerate(polys):
+                    a0, b0, n = self.inputs.offs[j.rid]
+                    desc[i] = (j.prime_id, j.size, j.size, 0, a0, b0, cpos)
+                    cpos += 2 * j.size + 1
+                plan = self.plans[slot]
+                plan.update(desc)
+                out = torch.empty(max(1, cpos), dtype=torch.int32, device=self.inputs.arena.device)
+                scr = torch.empty(max(1, (plan.scratch_bytes + 3) // 4), dtype=torch.int32,
+                                  device=self.inputs.arena.device)
+                plan.execute(self.inputs.arena, out, scr)
+                keep += [out, scr]
+                for i, j in enumerate(polys):
+                    c0 = int(desc["c_off"][i])
+                    j.result = out[c0:c0 + 2 * j.size + 1]
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return (ev, batch, keep)
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle) -> dict:
+        ev, batch, keep = handle
+        for j in batch:
+            if not _keeps(self.keep, j.rid):
+                j.result = None
+        return {}
+
+    def close(self):
+        for b in self.vecb:
+            b.close()
+        for p in self.plans:
+            p.close()
+
+
+class GpuPlainExecutor:
+    """Baseline: every request on its own with plain launches (mont_mul, or
+    ntt_polymul's one-to-three launches), in arrival order on one stream."""
+
+    def __init__(self, ctx, inputs: DeviceInputs, keep_results: bool = True):
+        import torch
+        from . import mont, ntt
+        self.torch, self.mont, self.ntt = torch, mont, ntt
+        self.ctx = ctx
+        self.inputs = inputs
+        self.keep = keep_results
+        self.params = [mont.setup(P) for P in ctx.primes]
+        self.stream = torch.cuda.Stream()
+
+    def footprint(self, job: Job) -> int:
+        if job.kind == "mul":
+            return 4 * job.size
+        return 4 * (2 * job.size + 1) + self.ntt.scratch_bytes(job.size, job.size)
+
+    def launch(self, slot: int, batch):
+        torch, mont, ntt = self.torch, self.mont, self.ntt
+        with torch.cuda.stream(self.stream):
+            for j in batch:
+                a, b = self.inputs.views(j.rid)
+                if j.kind == "mul":
+                    j.result = mont.mul(self.params[j.prime_id], a, b)
+                else:
+                    j.result = ntt.polymul(self.ctx, j.prime_id, a, b)
+            ev = torch.cuda.Event()
+            ev.record(self.stream)
+        return (ev, batch)
+
+    def poll(self, handle) -> bool:
+        return handle[0].query()
+
+    def finish(self, handle) -> dict:
+        for j in handle[1]:
+            if not _keeps(self.keep, j.rid):
+                j.result = None
+        return {}
+
+    def close(self):
+        pass
+
+
+def jobs_from_requests(reqs, timeout: float = float("inf")):
+    """Scheduler jobs for workloads.Request objects (kind, prime, size, arrival)."""
+    return [Job(r.rid, r.t_arrival, r.kind, r.prime_id, r.size, timeout=timeout) for r in reqs]

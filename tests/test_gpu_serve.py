@@ -1,0 +1,158 @@
+"""GPU parity of the batched elementwise launch, reusable plans and the
+serving loop (bit-exact against the oracle; alone equals in the mix)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_00999_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PRIMES = wl.PRIMES_NTT
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    from paper_1609_00999_amd import mont, ntt, serve
+    return mont, ntt, serve
+
+
+@pytest.fixture(scope="module")
+def ctx(mods):
+    c = mods[1].Context(PRIMES, 23)
+    yield c
+    c.close()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x).view(np.int32)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def test_vector_batch_uneven(mods):
+    mont = mods[0]
+    rng = np.random.default_rng(1)
+    sizes = [0, 1, 3, 4095, 4096, 4097, 10000, 123457, 1 << 20, 5, 0, 70000]
+    b = mont.Batch(len(sizes) + 4)
+    items, refs = [], []
+    for i, n in enumerate(sizes):
+        P = (list(wl.PRIMES_BW) + list(PRIMES))[i % 12]
+        prm = mont.setup(P)
+        a = rng.integers(0, P, n + 1, dtype=np.uint32)
+        c = rng.integers(0, P, n + 1, dtype=np.uint32)
+        off = i % 2                      # odd vectors start 4 bytes in: not 16-byte aligned
+        da, dc = dev(a)[off:off + n], dev(c)[off:off + n]
+        out = torch.empty(n + 1, dtype=torch.int32, device="cuda")[off:off + n]
+        items.append((prm, da, dc, out))
+        refs.append(oracle.mont_mul(P, a[off:off + n], c[off:off + n]))
+    b.update(items)
+    b.mul()
+    for (prm, _, _, out), ref in zip(items, refs):
+        assert np.array_equal(host(out), ref)
+    # a second, smaller batch through the same object
+    b.update(items[3:6])
+    for _, _, _, out in items[3:6]:
+        out.zero_()
+    b.mul()
+    for (prm, _, _, out), ref in zip(items[3:6], refs[3:6]):
+        assert np.array_equal(host(out), ref)
+    b.close()
+
+
+def test_vector_batch_errors(mods):
+    mont = mods[0]
+    b = mont.Batch(2)
+    x = torch.zeros(8, dtype=torch.int32, device="cuda")
+    prm = mont.setup(PRIMES[0])
+    with pytest.raises(mont.MontError) as ei:
+        b.update([(prm, x, x, x)] * 3)
+    assert ei.value.status == -2
+    bad = mont.MontParams(P=PRIMES[0], Pprime=7, R1=0, R2=0, k=0)
+    with pytest.raises(mont.MontError) as ei:
+        b.update([(bad, x, x, x)])
+    assert ei.value.status == -1
+    b.close()
+
+
+def test_reserved_plan_updates(mods, ctx):
+    ntt = mods[1]
+    rng = np.random.default_rng(2)
+    plan = ntt.Plan.reserve(ctx, 64, 1 << 16)
+    for rep, (lo, hi, count) in enumerate([(2, 16, 40), (10, 18, 12), (0, 6, 64)]):
+        da = wl.log_uniform(rng, lo, hi, count)
+        pid = rng.integers(0, len(PRIMES), count)
+        batch = wl.pack_products(PRIMES, pid, da, da, rng)
+        desc = ntt.make_descs(batch.prime_id, batch.da, batch.db, batch.a_off, batch.b_off, batch.c_off)
+        plan.update(desc, order_seed=rep)
+        din = dev(batch.coeffs)
+        out = torch.zeros(batch.out_len, dtype=torch.int32, device="cuda")
+        scr = plan.alloc_scratch()
+        plan.execute(din, out, scr)
+        assert plan.status(scr) == 0
+        got = host(out)
+        for i in range(batch.count):
+            P, a, b = batch.operands(i)
+            ref = oracle.polymul(P, a, b)
+            assert np.array_equal(got[batch.c_off[i]: batch.c_off[i] + ref.size], ref), (rep, i)
+    big = np.zeros(65, dtype=ntt.DESC_DTYPE)
+    with pytest.raises(Exception):
+        plan.update(big)
+    plan.close()
+
+
+def serve_setup(mods, ctx, count=48, seed=11):
+    serve = mods[2]
+    reqs = wl.request_stream(count, 1e6, seed=seed, mul_log2=(4, 17), poly_log2=(3, 15))
+    for r in reqs:
+        r.t_arrival = 0.0
+    inputs = serve.DeviceInputs(reqs, PRIMES)
+    return serve, reqs, inputs
+
+
+def oracle_result(inputs, r):
+    P = PRIMES[r.prime_id]
+    a, b = inputs.host_operands(r.rid)
+    return oracle.mont_mul(P, a, b) if r.kind == "mul" else oracle.polymul(P, a, b)
+
+
+def test_serving_batches_exact_and_alone_equals_mix(mods, ctx):
+    serve, reqs, inputs = serve_setup(mods, ctx)
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=3, max_batch=16)
+    stats = serve.Scheduler(ex, slots=3, budget_bytes=1 << 30, max_batch=16).run(serve.jobs_from_requests(reqs))
+    assert all(j.status == serve.OK for j in stats.jobs)
+    assert stats.batches < len(reqs)
+    mix = {j.rid: host(j.result) for j in stats.jobs}
+    for r in reqs:
+        assert np.array_equal(mix[r.rid], oracle_result(inputs, r)), r.rid
+    # every request alone through the same executor gives the same bytes
+    for r in reqs[::5]:
+        st = serve.Scheduler(ex, slots=3, budget_bytes=1 << 30).run(serve.jobs_from_requests([r]))
+        assert st.jobs[0].status == serve.OK
+        assert host(st.jobs[0].result).tobytes() == mix[r.rid].tobytes()
+    # the per-request plain-launch baseline agrees too
+    plain = serve.GpuPlainExecutor(ctx, inputs)
+    st = serve.Scheduler(plain, slots=1, budget_bytes=1 << 30, max_batch=1).run(serve.jobs_from_requests(reqs))
+    for j in st.jobs:
+        assert host(j.result).tobytes() == mix[j.rid].tobytes()
+    ex.close()
+
+
+def test_serving_under_tight_budget(mods, ctx):
+    serve, reqs, inputs = serve_setup(mods, ctx, count=30, seed=12)
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=2, max_batch=8)
+    fps = [ex.footprint(j) for j in serve.jobs_from_requests(reqs)]
+    budget = 2 * max(fps)
+    stats = serve.Scheduler(ex, slots=2, budget_bytes=budget, max_batch=8).run(serve.jobs_from_requests(reqs))
+    assert stats.max_inflight_bytes <= budget
+    assert all(j.status == serve.OK for j in stats.jobs)
+    for j in stats.jobs:
+        r = reqs[j.rid]
+        assert np.array_equal(host(j.result), oracle_result(inputs, r))
+    ex.close()
