@@ -1,0 +1,176 @@
+// batch.hip -- Montgomery products over a batch of vectors of uneven
+// lengths, each with its own modulus, in one persistent launch
+// (Algorithm 2 of arXiv:1609.00999, section 3.1, elementwise).
+#include <hip/hip_runtime.h>
+
+#include <new>
+
+#include "internal.hpp"
+#include "modarith.hpp"
+
+namespace mont {
+
+namespace {
+
+__device__ __forceinline__ bool aligned16_dev(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// ---------------------------------------------------------------------------
+// Batches of vectors of uneven lengths, each with its own modulus, in one
+// persistent launch.  The flattened work is cut into tiles of kBatchTile
+// residues that never straddle two vectors: vector v owns tiles
+// [tile_begin[v], tile_begin[v+1]).  A workgroup finds its tile's vector by
+// binary search and streams that tile with 128-bit accesses when the
+// vector's arrays are 16-byte aligned.
+// ---------------------------------------------------------------------------
+
+constexpr int kBatchThreads = 256;
+constexpr uint32_t kBatchTile = 4096;   // residues per tile: 4 per lane, 4 rounds
+
+struct VecDev {
+  const uint32_t* a;
+  const uint32_t* b;
+  uint32_t* out;
+  uint64_t n;
+  uint64_t tile_begin;
+  uint32_t P, Pp;
+};
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch_mul(const VecDev* vecs, uint32_t nvec, uint64_t ntiles) {
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    uint32_t lo = 0, hi = nvec - 1;             // last v with tile_begin[v] <= t
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (vecs[mid].tile_begin <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const VecDev v = vecs[lo];
+    const Mod md{v.P, v.Pp};
+    const uint64_t e0 = (t - v.tile_begin) * kBatchTile;
+    const uint64_t e1 = e0 + kBatchTile < v.n ? e0 + kBatchTile : v.n;
+    const bool al = aligned16_dev(v.a) && aligned16_dev(v.b) && aligned16_dev(v.out);
+    if (al && e1 - e0 == kBatchTile) {
+      const v4u* va = reinterpret_cast<const v4u*>(v.a + e0);
+      const v4u* vb = reinterpret_cast<const v4u*>(v.b + e0);
+      v4u* vo = reinterpret_cast<v4u*>(v.out + e0);
+      v4u x[4], y[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        x[j] = __builtin_nontemporal_load(va + j * kBatchThreads + threadIdx.x);
+        y[j] = __builtin_nontemporal_load(vb + j * kBatchThreads + threadIdx.x);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        v4u r;
+        r.x = mmul(x[j].x, y[j].x, md);
+        r.y = mmul(x[j].y, y[j].y, md);
+        r.z = mmul(x[j].z, y[j].z, md);
+        r.w = mmul(x[j].w, y[j].w, md);
+        __builtin_nontemporal_store(r, vo + j * kBatchThreads + threadIdx.x);
+      }
+    } else {
+      for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBatchThreads) v.out[e] = mmul(v.a[e], v.b[e], md);
+    }
+  }
+}
+
+}  // namespace
+
+}  // namespace mont
+
+using namespace mont;
+
+struct mont_batch {
+  int cap = 0;
+  int count = 0;
+  uint64_t ntiles = 0;
+  VecDev* d_vecs = nullptr;
+  VecDev* h_vecs = nullptr;       // pinned staging
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  int grid = 0;
+};
+
+namespace {
+
+void free_batch(mont_batch* b) {
+  (void)hipFree(b->d_vecs);
+  if (b->h_vecs) (void)hipHostFree(b->h_vecs);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" mont_status mont_batch_reserve(int max_vectors, mont_batch** out) {
+  if (!out || max_vectors < 1) return MONT_EINVAL;
+  *out = nullptr;
+  mont_batch* b = new (std::nothrow) mont_batch;
+  if (!b) return MONT_ENOMEM;
+  b->cap = max_vectors;
+  if (hipMalloc(&b->d_vecs, sizeof(VecDev) * max_vectors) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_vecs, sizeof(VecDev) * max_vectors, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
+    free_batch(b);
+    return MONT_ENOMEM;
+  }
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  b->grid = cus * 8;
+  *out = b;
+  return MONT_OK;
+}
+
+extern "C" mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* descs, int count, void* stream) {
+  if (!b || count < 0 || (count > 0 && !descs)) return MONT_EINVAL;
+  if (count > b->cap) return MONT_ERANGE;
+  for (int i = 0; i < count; i++) {
+    const mont_vec_desc& d = descs[i];
+    mont_params prm{d.P, d.Pprime, 0, 0, 0};
+    if (!params_ok(&prm)) return MONT_EINVAL;
+    if (d.n > 0 && (!d.a || !d.b || !d.out)) return MONT_EINVAL;
+  }
+  if (b->staged_pending && hipEventSynchronize(b->staged) != hipSuccess) return MONT_EHIP;
+  b->staged_pending = false;
+  uint64_t tiles = 0;
+  for (int i = 0; i < count; i++) {
+    const mont_vec_desc& d = descs[i];
+    VecDev& v = b->h_vecs[i];
+    v.a = d.a;
+    v.b = d.b;
+    v.out = d.out;
+    v.n = d.n;
+    v.tile_begin = tiles;
+    v.P = d.P;
+    v.Pp = d.Pprime;
+    tiles += (d.n + kBatchTile - 1) / kBatchTile;
+  }
+  b->count = count;
+  b->ntiles = tiles;
+  if (count > 0) {
+    hipStream_t s = as_stream(stream);
+    if (hipMemcpyAsync(b->d_vecs, b->h_vecs, sizeof(VecDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(b->staged, s) != hipSuccess)
+      return MONT_EHIP;
+    b->staged_pending = true;
+  }
+  return MONT_OK;
+}
+
+extern "C" mont_status mont_batch_mul(const mont_batch* b, void* stream) {
+  if (!b) return MONT_EINVAL;
+  if (b->count == 0 || b->ntiles == 0) return MONT_OK;
+  (void)hipGetLastError();
+  uint64_t grid = b->ntiles < (uint64_t)b->grid ? b->ntiles : (uint64_t)b->grid;
+  hipLaunchKernelGGL(k_batch_mul, dim3((unsigned)grid), dim3(kBatchThreads), 0, as_stream(stream), b->d_vecs,
+                     (uint32_t)b->count, b->ntiles);
+  return last_launch_status();
+}
+
+extern "C" mont_status mont_batch_destroy(mont_batch* b) {
+  if (!b) return MONT_EINVAL;
+  (void)hipDeviceSynchronize();
+  free_batch(b);
+  return MONT_OK;
+}
+
