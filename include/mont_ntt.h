@@ -164,6 +164,17 @@ MONT_API mont_status ntt_plan_status(const ntt_plan* plan, const void* d_scratch
 /* Frees the plan's device memory (synchronizes the device first). */
 MONT_API mont_status ntt_plan_destroy(ntt_plan* plan);
 
+/*
+ * Launch-shape tuning of the transform kernels (used by the autotuner):
+ * threads per workgroup (256, 512 or 1024), the largest number of radix-2
+ * stages a lane keeps in registers between LDS exchanges (3 or 4), and the
+ * default persistent grid as a multiple (1, 2 or 4) of the workgroups that
+ * fit on the device at once.  Process-wide, read when a launch is enqueued;
+ * never changes results.  Returns MONT_EINVAL for values outside those sets.
+ */
+MONT_API mont_status ntt_tune_set(int threads, int radix_log, int grid_mult);
+MONT_API mont_status ntt_tune_get(int* threads, int* radix_log, int* grid_mult);
+
 #ifdef __cplusplus
 }
 #endif

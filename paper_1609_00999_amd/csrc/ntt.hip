@@ -89,7 +89,6 @@ __device__ __forceinline__ Mod mod_of(const PrimeDev& pr) { return Mod{pr.P, pr.
 // twiddles per group instead of R 2^(R-1).
 // ---------------------------------------------------------------------------
 
-constexpr int kRadixLog = 4;           // at most 4 stages per LDS round
 
 // Twiddle tables are reached through pointers stored in device memory, so the
 // compiler cannot tell their address space; reading them as global memory
@@ -156,7 +155,7 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
   __syncthreads();
 }
 
-template <int NT, int NA, bool INV>
+template <int NT, int NA, bool INV, int RM>
 __device__ __forceinline__ void lds_round_r(int r, uint32_t* X, int off, uint32_t M, int s_lo, int lc, int rs,
                                             uint32_t colbase, const uint32_t* tw, Mod md) {
   switch (r) {
@@ -164,40 +163,41 @@ __device__ __forceinline__ void lds_round_r(int r, uint32_t* X, int off, uint32_
     case 2: lds_round<NT, NA, 2, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md); break;
     case 3: lds_round<NT, NA, 3, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md); break;
     default:
-      if constexpr (kRadixLog >= 4) lds_round<NT, NA, 4, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md);
+      if constexpr (RM >= 4) lds_round<NT, NA, 4, INV>(X, off, M, s_lo, lc, rs, colbase, tw, md);
       break;
   }
 }
 
-// Round sizes for lr stages: ceil(lr / kRadixLog) rounds, as even as
-// possible, the larger ones first.
+// Round sizes for lr stages: ceil(lr / RM) rounds of at most RM stages, as
+// even as possible, the larger ones first.
+template <int RM>
 __device__ __forceinline__ int round_size(int lr, int idx) {
-  const int nr = (lr + kRadixLog - 1) / kRadixLog;
+  const int nr = (lr + RM - 1) / RM;
   const int base = lr / nr, extra = lr % nr;
   return base + (idx < extra ? 1 : 0);
 }
 
 // Forward (decimation in frequency): stages lr-1 .. 0, rounds from the top.
-template <int NT, int NA>
+template <int NT, int NA, int RM>
 __device__ __forceinline__ void lds_dif(uint32_t* X, int off, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw,
                         Mod md) {
   const uint32_t M = 1u << (lr + lc);
   int s_hi = lr;
   for (int idx = 0; s_hi > 0; idx++) {
-    const int r = round_size(lr, idx);
+    const int r = round_size<RM>(lr, idx);
     s_hi -= r;
-    lds_round_r<NT, NA, false>(r, X, off, M, s_hi, lc, rs, colbase, tw, md);
+    lds_round_r<NT, NA, false, RM>(r, X, off, M, s_hi, lc, rs, colbase, tw, md);
   }
 }
 
 // Inverse (decimation in time): stages 0 .. lr-1, rounds from the bottom.
-template <int NT>
+template <int NT, int RM>
 __device__ __forceinline__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uint32_t colbase, const uint32_t* tw, Mod md) {
   const uint32_t M = 1u << (lr + lc);
   int s_lo = 0;
   for (int idx = 0; s_lo < lr; idx++) {
-    const int r = round_size(lr, idx);
-    lds_round_r<NT, 1, true>(r, X, 0, M, s_lo, lc, rs, colbase, tw, md);
+    const int r = round_size<RM>(lr, idx);
+    lds_round_r<NT, 1, true, RM>(r, X, 0, M, s_lo, lc, rs, colbase, tw, md);
     s_lo += r;
   }
 }
@@ -210,7 +210,7 @@ __device__ __forceinline__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uin
 // Whole product with N = 2^n <= 2^13: zero-padded loads, b scaled by R/N on
 // load, forward transforms of both, pointwise REDC (which removes one R and
 // leaves a b / N), inverse transform, store of the da + db + 1 coefficients.
-template <int NT>
+template <int NT, int RM>
 __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const uint32_t* a, uint32_t da, const uint32_t* b,
                                 uint32_t db, uint32_t* out, uint32_t* X) {
   const Mod md = mod_of(pr);
@@ -223,10 +223,10 @@ __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const
     B[e] = e <= db ? mmul(b[e], sc, md) : 0u;
   }
   __syncthreads();
-  if (n > 0) lds_dif<NT, 2>(A, (int)N, n, 0, 0, 0, pr.twf, md);
+  if (n > 0) lds_dif<NT, 2, RM>(A, (int)N, n, 0, 0, 0, pr.twf, md);
   for (uint32_t e = threadIdx.x; e < N; e += NT) A[e] = mmul(A[e], B[e], md);
   __syncthreads();
-  if (n > 0) lds_dit<NT>(A, n, 0, 0, 0, pr.twi, md);
+  if (n > 0) lds_dit<NT, RM>(A, n, 0, 0, 0, pr.twi, md);
   const uint32_t nout = da + db + 1;
   for (uint32_t e = threadIdx.x; e < nout; e += NT) out[e] = A[e];
   __syncthreads();
@@ -234,7 +234,7 @@ __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const
 
 // Forward column pass, tile t: rows k < 2^n1, columns t*C + c; the input is
 // zero beyond index dvalid; scale != 0 multiplies by REDC(x * scale) on load.
-template <int NT>
+template <int NT, int RM>
 __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t dvalid,
                              uint32_t scale, uint32_t* dst, uint32_t* X) {
   const Mod md = mod_of(pr);
@@ -249,7 +249,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
     X[e] = v;
   }
   __syncthreads();
-  lds_dif<NT, 1>(X, 0, n1, lc, kRowLog, colbase, pr.twf, md);
+  lds_dif<NT, 1, RM>(X, 0, n1, lc, kRowLog, colbase, pr.twf, md);
   for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     dst[i] = X[e];
@@ -259,7 +259,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
 
 // Inverse column pass, tile t: the last n1 inverse stages; stores only
 // indices < nout.
-template <int NT>
+template <int NT, int RM>
 __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t* dst,
                              uint32_t nout, uint32_t* X) {
   const Mod md = mod_of(pr);
@@ -272,7 +272,7 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
     X[e] = src[i];
   }
   __syncthreads();
-  lds_dit<NT>(X, n1, lc, kRowLog, colbase, pr.twi, md);
+  lds_dit<NT, RM>(X, n1, lc, kRowLog, colbase, pr.twi, md);
   for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     if (i < nout) dst[i] = X[e];
@@ -287,7 +287,7 @@ enum RowMode { ROW_POLY = 0, ROW_FWD = 1, ROW_INV = 2 };
 //   ROW_POLY: forward stages on A and B, A = REDC(A B), inverse stages on A;
 //   ROW_FWD:  forward stages on A;
 //   ROW_INV:  A scaled by REDC(x * prescale) on load, inverse stages on A.
-template <int NT>
+template <int NT, int RM>
 __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, uint32_t* gA, const uint32_t* gB,
                          uint32_t prescale, uint32_t* X) {
   const Mod md = mod_of(pr);
@@ -302,14 +302,14 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
   }
   __syncthreads();
   if (lr > 0) {
-    if (mode == ROW_POLY) lds_dif<NT, 2>(A, (int)L, lr, 0, 0, 0, pr.twf, md);
-    else if (mode == ROW_FWD) lds_dif<NT, 1>(A, 0, lr, 0, 0, 0, pr.twf, md);
+    if (mode == ROW_POLY) lds_dif<NT, 2, RM>(A, (int)L, lr, 0, 0, 0, pr.twf, md);
+    else if (mode == ROW_FWD) lds_dif<NT, 1, RM>(A, 0, lr, 0, 0, 0, pr.twf, md);
   }
   if (mode == ROW_POLY) {
     for (uint32_t e = threadIdx.x; e < L; e += NT) A[e] = mmul(A[e], B[e], md);
     __syncthreads();
   }
-  if (mode != ROW_FWD && lr > 0) lds_dit<NT>(A, lr, 0, 0, 0, pr.twi, md);
+  if (mode != ROW_FWD && lr > 0) lds_dit<NT, RM>(A, lr, 0, 0, 0, pr.twi, md);
   for (uint32_t e = threadIdx.x; e < L; e += NT) gA[e] = A[e];
   __syncthreads();
 }
@@ -318,7 +318,6 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
 // Kernels.
 // ---------------------------------------------------------------------------
 
-constexpr int kThreads = 512;
 
 // Plain launches: one task per workgroup, the task index is blockIdx.x.
 struct DirectArgs {
@@ -346,27 +345,27 @@ enum DirectKind : uint32_t {
   D_COLI_INPLACE = 9,
 };
 
-template <int NT>
-__global__ __launch_bounds__(NT, 4) void k_ntt_direct(DirectArgs g) {
+template <int NT, int RM>
+__global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_direct(DirectArgs g) {
   __shared__ uint32_t X[kLdsWords];
   const PrimeDev& pr = g.primes[g.prime_id];
   const uint32_t bid = blockIdx.x;
   const uint32_t N = 1u << g.n;
   const uint32_t S = 1u << kRowLog;
   switch (g.kind) {
-    case D_SMALL_POLY: exec_small_poly<NT>(pr, g.n, g.a, g.da, g.b, g.db, g.out, X); break;
+    case D_SMALL_POLY: exec_small_poly<NT, RM>(pr, g.n, g.a, g.da, g.b, g.db, g.out, X); break;
     case D_COLF:
-      if (bid < g.ntiles) exec_col_dif<NT>(pr, g.n, g.lc, bid, g.a, g.da, 0u, g.scr, X);
-      else exec_col_dif<NT>(pr, g.n, g.lc, bid - g.ntiles, g.b, g.db, pr.s2[g.n], g.scr + N, X);
+      if (bid < g.ntiles) exec_col_dif<NT, RM>(pr, g.n, g.lc, bid, g.a, g.da, 0u, g.scr, X);
+      else exec_col_dif<NT, RM>(pr, g.n, g.lc, bid - g.ntiles, g.b, g.db, pr.s2[g.n], g.scr + N, X);
       break;
-    case D_ROW_POLY: exec_row<NT>(pr, kRowLog, ROW_POLY, g.scr + bid * S, g.scr + N + bid * S, 0u, X); break;
-    case D_COLI: exec_col_dit<NT>(pr, g.n, g.lc, bid, g.scr, g.out, g.da + g.db + 1, X); break;
-    case D_FWD_SMALL: exec_row<NT>(pr, g.n, ROW_FWD, g.out, nullptr, 0u, X); break;
-    case D_INV_SMALL: exec_row<NT>(pr, g.n, ROW_INV, g.out, nullptr, g.prescale, X); break;
-    case D_COLF_INPLACE: exec_col_dif<NT>(pr, g.n, g.lc, bid, g.out, N - 1, 0u, g.out, X); break;
-    case D_ROW_FWD: exec_row<NT>(pr, kRowLog, ROW_FWD, g.out + bid * S, nullptr, 0u, X); break;
-    case D_ROW_INV: exec_row<NT>(pr, kRowLog, ROW_INV, g.out + bid * S, nullptr, g.prescale, X); break;
-    default: exec_col_dit<NT>(pr, g.n, g.lc, bid, g.out, g.out, N, X); break;
+    case D_ROW_POLY: exec_row<NT, RM>(pr, kRowLog, ROW_POLY, g.scr + bid * S, g.scr + N + bid * S, 0u, X); break;
+    case D_COLI: exec_col_dit<NT, RM>(pr, g.n, g.lc, bid, g.scr, g.out, g.da + g.db + 1, X); break;
+    case D_FWD_SMALL: exec_row<NT, RM>(pr, g.n, ROW_FWD, g.out, nullptr, 0u, X); break;
+    case D_INV_SMALL: exec_row<NT, RM>(pr, g.n, ROW_INV, g.out, nullptr, g.prescale, X); break;
+    case D_COLF_INPLACE: exec_col_dif<NT, RM>(pr, g.n, g.lc, bid, g.out, N - 1, 0u, g.out, X); break;
+    case D_ROW_FWD: exec_row<NT, RM>(pr, kRowLog, ROW_FWD, g.out + bid * S, nullptr, 0u, X); break;
+    case D_ROW_INV: exec_row<NT, RM>(pr, kRowLog, ROW_INV, g.out + bid * S, nullptr, g.prescale, X); break;
+    default: exec_col_dit<NT, RM>(pr, g.n, g.lc, bid, g.out, g.out, N, X); break;
   }
 }
 
@@ -410,8 +409,8 @@ __device__ __forceinline__ bool wait_count(uint32_t* ctr, uint32_t need, uint32_
 // wave's outstanding global stores have been acknowledged by L2.
 constexpr int kWaitVmcnt0 = 0x0F70;
 
-template <int NT>
-__global__ __launch_bounds__(NT, 4) void k_ntt_persistent(PlanArgs g) {
+template <int NT, int RM>
+__global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persistent(PlanArgs g) {
   __shared__ uint32_t X[kLdsWords];
   __shared__ uint32_t s_task, s_go;
   uint32_t* head = g.scr;
@@ -442,14 +441,14 @@ __global__ __launch_bounds__(NT, 4) void k_ntt_persistent(PlanArgs g) {
     if (s_go) {
       switch (kind) {
         case T_SMALL:
-          exec_small_poly<NT>(pr, pd.n, g.in + pd.a_off, pd.da, g.in + pd.b_off, pd.db, g.out + pd.c_off, X);
+          exec_small_poly<NT, RM>(pr, pd.n, g.in + pd.a_off, pd.da, g.in + pd.b_off, pd.db, g.out + pd.c_off, X);
           break;
-        case T_COLF_A: exec_col_dif<NT>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X); break;
+        case T_COLF_A: exec_col_dif<NT, RM>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X); break;
         case T_COLF_B:
-          exec_col_dif<NT>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X);
+          exec_col_dif<NT, RM>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X);
           break;
-        case T_ROW: exec_row<NT>(pr, kRowLog, ROW_POLY, scr + idx * S, scr + N + idx * S, 0u, X); break;
-        default: exec_col_dit<NT>(pr, pd.n, pd.lc, idx, scr, g.out + pd.c_off, pd.da + pd.db + 1, X); break;
+        case T_ROW: exec_row<NT, RM>(pr, kRowLog, ROW_POLY, scr + idx * S, scr + N + idx * S, 0u, X); break;
+        default: exec_col_dit<NT, RM>(pr, pd.n, pd.lc, idx, scr, g.out + pd.c_off, pd.da + pd.db + 1, X); break;
       }
       if (kind != T_SMALL && kind != T_COLI) {
         // Publish this task's stores at agent scope before counting it: every
@@ -608,8 +607,68 @@ namespace {
 
 mont_status hip_ok(hipError_t e) { return e == hipSuccess ? MONT_OK : MONT_EHIP; }
 
+// Launch shape of the transform kernels: threads per workgroup and the
+// largest radix-2^R round.  Process-wide; read when a launch is enqueued.
+struct NttTune {
+  int threads;
+  int radix_log;
+  int grid_mult;   // persistent grid = resident workgroups x grid_mult
+};
+NttTune g_ntt_tune = {512, 4, 1};
+
+template <int NT, int RM>
+void launch_direct_v(const DirectArgs& g, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_ntt_direct<NT, RM>), dim3(grid), dim3(NT), 0, s, g);
+}
+
+template <int NT, int RM>
+void launch_persistent_v(const PlanArgs& g, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_ntt_persistent<NT, RM>), dim3(grid), dim3(NT), 0, s, g);
+}
+
+template <int NT, int RM>
+int occupancy_v() {
+  int per_cu = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ntt_persistent<NT, RM>, NT, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu;
+}
+
+#define MONT_NTT_VARIANTS(X) X(256, 3) X(256, 4) X(512, 3) X(512, 4) X(1024, 3) X(1024, 4)
+
 void launch_direct(const DirectArgs& g, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_ntt_direct<kThreads>), dim3(grid), dim3(kThreads), 0, s, g);
+#define MONT_V(T, R)                                                      \
+  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) {             \
+    launch_direct_v<T, R>(g, grid, s);                                    \
+    return;                                                               \
+  }
+  MONT_NTT_VARIANTS(MONT_V)
+#undef MONT_V
+  launch_direct_v<512, 4>(g, grid, s);
+}
+
+void launch_persistent(const PlanArgs& g, uint32_t grid, hipStream_t s) {
+#define MONT_V(T, R)                                                      \
+  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) {             \
+    launch_persistent_v<T, R>(g, grid, s);                                \
+    return;                                                               \
+  }
+  MONT_NTT_VARIANTS(MONT_V)
+#undef MONT_V
+  launch_persistent_v<512, 4>(g, grid, s);
+}
+
+// Resident persistent workgroups for the current launch shape.
+int persistent_grid() {
+  int dev = 0, cus = 256, per_cu = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+#define MONT_V(T, R) \
+  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) per_cu = occupancy_v<T, R>();
+  MONT_NTT_VARIANTS(MONT_V)
+#undef MONT_V
+  return cus * per_cu * g_ntt_tune.grid_mult;
 }
 
 bool prime_ok(const ntt_ctx* ctx, int prime_id) {
@@ -630,6 +689,22 @@ DirectArgs direct_base(const ntt_ctx* ctx, int prime_id, int n) {
 }
 
 }  // namespace
+
+extern "C" mont_status ntt_tune_set(int threads, int radix_log, int grid_mult) {
+  if ((threads != 256 && threads != 512 && threads != 1024) || (radix_log != 3 && radix_log != 4) ||
+      (grid_mult != 1 && grid_mult != 2 && grid_mult != 4))
+    return MONT_EINVAL;
+  g_ntt_tune = NttTune{threads, radix_log, grid_mult};
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_tune_get(int* threads, int* radix_log, int* grid_mult) {
+  if (!threads || !radix_log || !grid_mult) return MONT_EINVAL;
+  *threads = g_ntt_tune.threads;
+  *radix_log = g_ntt_tune.radix_log;
+  *grid_mult = g_ntt_tune.grid_mult;
+  return MONT_OK;
+}
 
 extern "C" mont_status ntt_ctx_create(const uint32_t* primes, int nprimes, int log2_nmax, ntt_ctx** out) {
   if (!out || !primes || nprimes <= 0 || nprimes > 64 || log2_nmax < 1 || log2_nmax > kMaxLog) return MONT_EINVAL;
@@ -897,16 +972,6 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   return MONT_OK;
 }
 
-int persistent_grid() {
-  int dev = 0, cus = 256, per_cu = 1;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_ntt_persistent<kThreads>, kThreads, 0) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  return cus * per_cu;
-}
-
 void free_plan(ntt_plan* plan) {
   (void)hipFree(plan->d_prods);
   (void)hipFree(plan->d_tasks);
@@ -1022,7 +1087,7 @@ extern "C" mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes
   if (ntasks) *ntasks = plan->ntasks;
   if (in_words) *in_words = plan->in_words;
   if (out_words) *out_words = plan->out_words;
-  if (default_grid) *default_grid = plan->default_grid;
+  if (default_grid) *default_grid = persistent_grid();
   return MONT_OK;
 }
 
@@ -1048,9 +1113,9 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   g.out = d_out;
   g.scr = scr;
   g.spin_limit = spin_limit ? spin_limit : (1u << 24);
-  uint32_t gsz = grid > 0 ? (uint32_t)grid : (uint32_t)plan->default_grid;
+  uint32_t gsz = grid > 0 ? (uint32_t)grid : (uint32_t)persistent_grid();
   gsz = std::max(1u, std::min(gsz, plan->ntasks));
-  hipLaunchKernelGGL((k_ntt_persistent<kThreads>), dim3(gsz), dim3(kThreads), 0, s, g);
+  launch_persistent(g, gsz, s);
   return last_launch_status();
 }
 

@@ -61,7 +61,23 @@ def lib() -> ctypes.CDLL:
     L.mont_elem_tune_get.argtypes = [ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3
     _register_ntt(L)
     _lib = L
+    _apply_tuning(L)
     return L
+
+
+def _apply_tuning(L) -> None:
+    """Apply the autotuner's cached launch shapes for this GPU (MONT_TUNE=0
+    keeps the built-in defaults)."""
+    if os.environ.get("MONT_TUNE", "1") == "0":
+        return
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return
+        from . import tune
+        tune.applied = tune.apply(tune.load(), tune.device_arch(), L)
+    except Exception:   # tuning is an optimisation; defaults stay in force
+        pass
 
 
 def _register_ntt(L):

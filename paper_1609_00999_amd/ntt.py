@@ -38,6 +38,8 @@ def register(L) -> None:
     L.ntt_ctx_destroy.argtypes = [c_vp]
     L.ntt_ctx_prime.argtypes = [c_vp, c_int, pp, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32), vpp, vpp]
     L.ntt_ctx_read_twiddles.argtypes = [c_vp, c_int, c_vp, c_vp]
+    L.ntt_tune_set.argtypes = [c_int, c_int, c_int]
+    L.ntt_tune_get.argtypes = [ctypes.POINTER(c_int)] * 3
     L.ntt_forward.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp]
     L.ntt_inverse.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp]
     L.ntt_polymul_scratch_bytes.argtypes = [c_u32, c_u32]
@@ -127,6 +129,16 @@ def inverse(ctx: Context, prime_id: int, x):
     mont.check(mont.lib().ntt_inverse(ctx.handle, prime_id, mont.dev_ptr(x, "x"), logn, mont.stream_handle()),
                "ntt_inverse")
     return x
+
+
+def tune_set(threads: int, radix_log: int, grid_mult: int = 1) -> None:
+    mont.check(mont.lib().ntt_tune_set(threads, radix_log, grid_mult), "ntt_tune_set")
+
+
+def tune_get():
+    t, r, g = c_int(), c_int(), c_int()
+    mont.check(mont.lib().ntt_tune_get(ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)), "ntt_tune_get")
+    return t.value, r.value, g.value
 
 
 def scratch_bytes(da: int, db: int) -> int:

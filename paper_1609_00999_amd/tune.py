@@ -1,0 +1,190 @@
+"""Autotuner for libmont's launch shapes.
+
+It times the candidate launch shapes of a kernel family on the device and
+keeps the fastest, caching the choice as JSON keyed by GPU architecture,
+kernel family and workload bucket.  The library applies the cache for the
+running architecture when it is first loaded (``apply``), so later plans and
+launches use the tuned shapes.  Launch shapes never change results (the GPU
+tests check every shape against the oracle).
+
+Tuned knobs:
+  * elementwise (per op: to, from, mul, muladd, pow): threads per workgroup
+    {256, 512} x 128-bit vectors per lane {1, 2, 4} x non-temporal {0, 1};
+  * transforms (one setting for all transform kernels): threads per
+    workgroup {256, 512, 1024} x largest register round {3, 4} stages, and
+    the persistent grid as a multiple of the resident workgroup count.
+
+Usage:  python -m paper_1609_00999_amd.tune [--out PATH] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(PKG, "tune_cache.json")
+
+ELEM_SHAPES = [(b, v, nt) for b in (256, 512) for v in (1, 2, 4) for nt in (1, 0)]
+NTT_SHAPES = [(t, r) for t in (256, 512, 1024) for r in (3, 4)]
+GRID_MULTS = (1, 2)
+applied: dict = {}
+
+
+def cache_path() -> str:
+    return os.environ.get("MONT_TUNE_CACHE", DEFAULT_CACHE)
+
+
+def load(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            data = json.load(f)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save(cache: dict, path: str | None = None) -> str:
+    path = path or cache_path()
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return path
+
+
+def merge(cache: dict, arch: str, family: str, bucket: str, entry: dict) -> dict:
+    cache.setdefault(arch, {}).setdefault(family, {})[bucket] = entry
+    return cache
+
+
+def best_entry(results):
+    """results: list of (config, seconds); the fastest, with every measurement."""
+    cfg, sec = min(results, key=lambda r: r[1])
+    return {"config": list(cfg), "seconds": sec, "measured": [[list(c), s] for c, s in results]}
+
+
+def choose(cache: dict, arch: str, family: str):
+    """The tuned config of a family for an architecture: the entry of the
+    largest numeric bucket (the bench sizes), or None."""
+    fam = cache.get(arch, {}).get(family, {})
+    if not fam:
+        return None
+    key = max(fam, key=lambda k: int(k) if k.lstrip("-").isdigit() else -1)
+    return fam[key]["config"]
+
+
+def apply(cache: dict, arch: str, lib) -> dict:
+    """Set the tuned launch shapes of `arch` through the C ABI; returns what
+    was applied."""
+    applied = {}
+    for op, idx in (("to", 0), ("from", 1), ("mul", 2), ("muladd", 3), ("pow", 4)):
+        cfg = choose(cache, arch, "elem_" + op)
+        if cfg and lib.mont_elem_tune_set(idx, int(cfg[0]), int(cfg[1]), int(cfg[2])) == 0:
+            applied["elem_" + op] = cfg
+    cfg = choose(cache, arch, "ntt")
+    if cfg and lib.ntt_tune_set(int(cfg[0]), int(cfg[1]), int(cfg[2])) == 0:
+        applied["ntt"] = cfg
+    return applied
+
+
+# ---------------------------------------------------------------------------
+# measurement (needs the GPU)
+# ---------------------------------------------------------------------------
+
+def device_arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _time(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def tune_elementwise(n_log2: int = 28, reps: int = 5, ops=("to", "from", "mul", "muladd", "pow")):
+    import torch
+    from . import mont
+    n = 1 << n_log2
+    P = 2013265921
+    prm = mont.setup(P)
+    g = torch.Generator(device="cuda").manual_seed(7)
+    a = torch.randint(0, P, (n,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
+    b = torch.randint(0, P, (n,), generator=g, device="cuda", dtype=torch.int64).to(torch.int32)
+    c = torch.empty_like(a)
+    o = torch.empty_like(a)
+    calls = {"to": lambda: mont.to_mont(prm, a, out=o), "from": lambda: mont.from_mont(prm, a, out=o),
+             "mul": lambda: mont.mul(prm, a, b, out=o), "muladd": lambda: mont.muladd(prm, a, b, c, out=o),
+             "pow": lambda: mont.pow(prm, a, b, out=o)}
+    out = {}
+    for op in ops:
+        old = mont.elem_tune_get(op)
+        res = []
+        for shape in ELEM_SHAPES:
+            mont.elem_tune_set(op, *shape)
+            res.append((shape, _time(torch, calls[op], reps)))
+        best = best_entry(res) if res else None
+        if best:
+            mont.elem_tune_set(op, *best["config"])
+            out[op] = best
+        else:
+            mont.elem_tune_set(op, *old)
+    return out
+
+
+def tune_ntt(batch=None, reps: int = 3):
+    import torch
+    from . import mont, ntt
+    from . import workloads as wl
+    batch = batch or wl.polymul_batch()
+    ctx = ntt.Context(wl.PRIMES_NTT, 23)
+    plan = ntt.Plan.from_batch(ctx, batch)
+    din = torch.from_numpy(batch.coeffs.view(np.int32)).cuda()
+    dout = torch.empty(batch.out_len, dtype=torch.int32, device="cuda")
+    scr = plan.alloc_scratch()
+    L = mont.lib()
+    res = []
+    for threads, radix in NTT_SHAPES:
+        for gm in GRID_MULTS:
+            mont.check(L.ntt_tune_set(threads, radix, gm), "ntt_tune_set")
+            t = _time(torch, lambda: plan.execute(din, dout, scr), reps)
+            res.append(((threads, radix, gm), t))
+    best = best_entry(res)
+    mont.check(L.ntt_tune_set(*best["config"]), "ntt_tune_set")
+    plan.close()
+    ctx.close()
+    return best
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=cache_path())
+    ap.add_argument("--quick", action="store_true", help="smaller elementwise size (2^24)")
+    args = ap.parse_args()
+    arch = device_arch()
+    cache = load(args.out)
+    t0 = time.time()
+    n_log2 = 24 if args.quick else 28
+    for op, entry in tune_elementwise(n_log2).items():
+        merge(cache, arch, "elem_" + op, str(n_log2), entry)
+        print("elem_%s 2^%d -> %s (%.1f us)" % (op, n_log2, entry["config"], entry["seconds"] * 1e6), flush=True)
+    entry = tune_ntt()
+    merge(cache, arch, "ntt", "batch2048", entry)
+    print("ntt batch2048 -> %s (%.3f ms)" % (entry["config"], entry["seconds"] * 1e3), flush=True)
+    print("saved %s in %.1f s" % (save(cache, args.out), time.time() - t0))
+
+
+if __name__ == "__main__":
+    main()

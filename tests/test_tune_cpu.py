@@ -1,0 +1,57 @@
+"""The autotuner's cache logic without a GPU."""
+import os
+
+from paper_1609_00999_amd import tune
+
+
+class FakeLib:
+    def __init__(self):
+        self.calls = []
+
+    def mont_elem_tune_set(self, op, block, vpt, nt):
+        self.calls.append(("elem", op, block, vpt, nt))
+        return 0
+
+    def ntt_tune_set(self, threads, radix, gm):
+        self.calls.append(("ntt", threads, radix, gm))
+        return 0
+
+
+def test_best_entry_and_choose(tmp_path):
+    res = [((256, 1, 1), 3.0), ((512, 2, 0), 1.0), ((256, 4, 1), 2.0)]
+    e = tune.best_entry(res)
+    assert e["config"] == [512, 2, 0] and e["seconds"] == 1.0 and len(e["measured"]) == 3
+    cache = {}
+    tune.merge(cache, "gfx950", "elem_mul", "24", {"config": [256, 1, 1]})
+    tune.merge(cache, "gfx950", "elem_mul", "28", {"config": [512, 4, 0]})
+    assert tune.choose(cache, "gfx950", "elem_mul") == [512, 4, 0]     # the largest bucket
+    assert tune.choose(cache, "gfx942", "elem_mul") is None
+    path = os.path.join(str(tmp_path), "c.json")
+    tune.save(cache, path)
+    assert tune.load(path) == cache
+    assert tune.load(os.path.join(str(tmp_path), "missing.json")) == {}
+
+
+def test_apply_uses_the_c_abi():
+    cache = {"gfx950": {"elem_mul": {"28": {"config": [512, 2, 1]}}, "ntt": {"batch2048": {"config": [1024, 3, 2]}}}}
+    lib = FakeLib()
+    applied = tune.apply(cache, "gfx950", lib)
+    assert applied == {"elem_mul": [512, 2, 1], "ntt": [1024, 3, 2]}
+    assert ("elem", 2, 512, 2, 1) in lib.calls and ("ntt", 1024, 3, 2) in lib.calls
+    assert tune.apply(cache, "gfx90a", FakeLib()) == {}
+
+
+def test_shape_sets_match_the_abi():
+    import ctypes
+    from paper_1609_00999_amd import mont
+    L = mont.lib()
+    for b, v, nt in tune.ELEM_SHAPES:
+        assert L.mont_elem_tune_set(2, b, v, nt) == 0
+    for t, r in tune.NTT_SHAPES:
+        for g in tune.GRID_MULTS:
+            assert L.ntt_tune_set(t, r, g) == 0
+    assert L.ntt_tune_set(128, 3, 1) == -1 and L.ntt_tune_set(512, 5, 1) == -1 and L.ntt_tune_set(512, 4, 3) == -1
+    t, r, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    assert L.ntt_tune_get(ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)) == 0
+    L.ntt_tune_set(512, 4, 1)
+    L.mont_elem_tune_set(2, 256, 1, 1)
