@@ -73,6 +73,18 @@ namespace {
 
 __device__ __forceinline__ Mod mod_of(const PrimeDev& pr) { return Mod{pr.P, pr.Pp}; }
 
+// LDS word addressing.  Every access to a workgroup's LDS buffer goes through
+// lds_at(i), which XORs the low six bits of the word index with 13 times its
+// 64-word row (a bijection inside each row).  With 64 banks this spreads the
+// strided accesses of the low-stage rounds (lanes 8 or 16 words apart, or
+// groups of 8 or 16 lanes 64+ words apart) over the banks: the worst wave
+// access is 2-way instead of 16-way.
+constexpr bool kSwizzle = true;
+__device__ __forceinline__ uint32_t lds_at(uint32_t i) {
+  if constexpr (kSwizzle) return i ^ (((i >> 6) * 13u) & 63u);
+  else return i;
+}
+
 // ---------------------------------------------------------------------------
 // LDS stages.  X is viewed as rows x C columns (C = 2^lc, element (k, c) at
 // X[k*C + c]); the transform runs along rows, independently per column.  The
@@ -118,10 +130,10 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
         w[(1 << t) - 1 + jj] = ldg(tw, (1u << (s_lo + t + rs)) + t0 + ((uint32_t)jj << (s_lo + rs)));
 #pragma nounroll
     for (int a = 0; a < NA; a++) {
-      uint32_t* Y = X + a * off + base;
+      const uint32_t yb = (uint32_t)(a * off) + base;
       uint32_t v[E];
 #pragma unroll
-      for (int j = 0; j < E; j++) v[j] = Y[(uint32_t)j << a_lo];
+      for (int j = 0; j < E; j++) v[j] = X[lds_at(yb + ((uint32_t)j << a_lo))];
       if constexpr (!INV) {
 #pragma unroll
         for (int t = R - 1; t >= 0; t--) {
@@ -131,7 +143,8 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
             if (j & d) continue;
             const uint32_t x = v[j], y = v[j + d];
             v[j] = madd(x, y, md.P);
-            v[j + d] = mmul(msub(x, y, md.P), w[d - 1 + (j & (d - 1))], md);
+            // x - y + P is in [1, 2P): REDC takes it as is ((2P) P < R P)
+            v[j + d] = mmul(x - y + md.P, w[d - 1 + (j & (d - 1))], md);
           }
         }
       } else {
@@ -149,7 +162,7 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
         }
       }
 #pragma unroll
-      for (int j = 0; j < E; j++) Y[(uint32_t)j << a_lo] = v[j];
+      for (int j = 0; j < E; j++) X[lds_at(yb + ((uint32_t)j << a_lo))] = v[j];
     }
   }
   __syncthreads();
@@ -202,6 +215,17 @@ __device__ __forceinline__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uin
   }
 }
 
+// Stores whose data another workgroup reads later in the same persistent
+// launch are agent-scope atomic stores (global_store ... sc1): they are
+// written through to the device coherence point, so a consumer on another
+// XCD sees them once they have completed, and no L2 write-back is needed
+// when the task is published.
+template <bool COH>
+__device__ __forceinline__ void st_out(uint32_t* p, uint32_t v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
 // ---------------------------------------------------------------------------
 // Task bodies.  Every thread of the workgroup calls them (they contain
 // barriers); X is the workgroup's LDS buffer of kLdsWords words.
@@ -215,26 +239,24 @@ __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const
                                 uint32_t db, uint32_t* out, uint32_t* X) {
   const Mod md = mod_of(pr);
   const uint32_t N = 1u << n;
-  uint32_t* A = X;
-  uint32_t* B = X + N;
   const uint32_t sc = pr.s2[n];
   for (uint32_t e = threadIdx.x; e < N; e += NT) {
-    A[e] = e <= da ? a[e] : 0u;
-    B[e] = e <= db ? mmul(b[e], sc, md) : 0u;
+    X[lds_at(e)] = e <= da ? a[e] : 0u;
+    X[lds_at(N + e)] = e <= db ? mmul(b[e], sc, md) : 0u;
   }
   __syncthreads();
-  if (n > 0) lds_dif<NT, 2, RM>(A, (int)N, n, 0, 0, 0, pr.twf, md);
-  for (uint32_t e = threadIdx.x; e < N; e += NT) A[e] = mmul(A[e], B[e], md);
+  if (n > 0) lds_dif<NT, 2, RM>(X, (int)N, n, 0, 0, 0, pr.twf, md);
+  for (uint32_t e = threadIdx.x; e < N; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(N + e)], md);
   __syncthreads();
-  if (n > 0) lds_dit<NT, RM>(A, n, 0, 0, 0, pr.twi, md);
+  if (n > 0) lds_dit<NT, RM>(X, n, 0, 0, 0, pr.twi, md);
   const uint32_t nout = da + db + 1;
-  for (uint32_t e = threadIdx.x; e < nout; e += NT) out[e] = A[e];
+  for (uint32_t e = threadIdx.x; e < nout; e += NT) out[e] = X[lds_at(e)];
   __syncthreads();
 }
 
 // Forward column pass, tile t: rows k < 2^n1, columns t*C + c; the input is
 // zero beyond index dvalid; scale != 0 multiplies by REDC(x * scale) on load.
-template <int NT, int RM>
+template <int NT, int RM, bool COH>
 __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t dvalid,
                              uint32_t scale, uint32_t* dst, uint32_t* X) {
   const Mod md = mod_of(pr);
@@ -246,13 +268,13 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     uint32_t v = i <= dvalid ? src[i] : 0u;
     if (scale) v = mmul(v, scale, md);
-    X[e] = v;
+    X[lds_at(e)] = v;
   }
   __syncthreads();
   lds_dif<NT, 1, RM>(X, 0, n1, lc, kRowLog, colbase, pr.twf, md);
   for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
-    dst[i] = X[e];
+    st_out<COH>(dst + i, X[lds_at(e)]);
   }
   __syncthreads();
 }
@@ -269,13 +291,13 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
   const uint32_t cmask = (1u << lc) - 1;
   for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
-    X[e] = src[i];
+    X[lds_at(e)] = src[i];
   }
   __syncthreads();
   lds_dit<NT, RM>(X, n1, lc, kRowLog, colbase, pr.twi, md);
   for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
-    if (i < nout) dst[i] = X[e];
+    if (i < nout) dst[i] = X[lds_at(e)];
   }
   __syncthreads();
 }
@@ -287,30 +309,28 @@ enum RowMode { ROW_POLY = 0, ROW_FWD = 1, ROW_INV = 2 };
 //   ROW_POLY: forward stages on A and B, A = REDC(A B), inverse stages on A;
 //   ROW_FWD:  forward stages on A;
 //   ROW_INV:  A scaled by REDC(x * prescale) on load, inverse stages on A.
-template <int NT, int RM>
+template <int NT, int RM, bool COH>
 __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, uint32_t* gA, const uint32_t* gB,
                          uint32_t prescale, uint32_t* X) {
   const Mod md = mod_of(pr);
   const uint32_t L = 1u << lr;
-  uint32_t* A = X;
-  uint32_t* B = X + L;
   for (uint32_t e = threadIdx.x; e < L; e += NT) {
     uint32_t v = gA[e];
     if (mode == ROW_INV && prescale) v = mmul(v, prescale, md);
-    A[e] = v;
-    if (mode == ROW_POLY) B[e] = gB[e];
+    X[lds_at(e)] = v;
+    if (mode == ROW_POLY) X[lds_at(L + e)] = gB[e];
   }
   __syncthreads();
   if (lr > 0) {
-    if (mode == ROW_POLY) lds_dif<NT, 2, RM>(A, (int)L, lr, 0, 0, 0, pr.twf, md);
-    else if (mode == ROW_FWD) lds_dif<NT, 1, RM>(A, 0, lr, 0, 0, 0, pr.twf, md);
+    if (mode == ROW_POLY) lds_dif<NT, 2, RM>(X, (int)L, lr, 0, 0, 0, pr.twf, md);
+    else if (mode == ROW_FWD) lds_dif<NT, 1, RM>(X, 0, lr, 0, 0, 0, pr.twf, md);
   }
   if (mode == ROW_POLY) {
-    for (uint32_t e = threadIdx.x; e < L; e += NT) A[e] = mmul(A[e], B[e], md);
+    for (uint32_t e = threadIdx.x; e < L; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(L + e)], md);
     __syncthreads();
   }
-  if (mode != ROW_FWD && lr > 0) lds_dit<NT, RM>(A, lr, 0, 0, 0, pr.twi, md);
-  for (uint32_t e = threadIdx.x; e < L; e += NT) gA[e] = A[e];
+  if (mode != ROW_FWD && lr > 0) lds_dit<NT, RM>(X, lr, 0, 0, 0, pr.twi, md);
+  for (uint32_t e = threadIdx.x; e < L; e += NT) st_out<COH>(gA + e, X[lds_at(e)]);
   __syncthreads();
 }
 
@@ -355,16 +375,16 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_direct(Di
   switch (g.kind) {
     case D_SMALL_POLY: exec_small_poly<NT, RM>(pr, g.n, g.a, g.da, g.b, g.db, g.out, X); break;
     case D_COLF:
-      if (bid < g.ntiles) exec_col_dif<NT, RM>(pr, g.n, g.lc, bid, g.a, g.da, 0u, g.scr, X);
-      else exec_col_dif<NT, RM>(pr, g.n, g.lc, bid - g.ntiles, g.b, g.db, pr.s2[g.n], g.scr + N, X);
+      if (bid < g.ntiles) exec_col_dif<NT, RM, false>(pr, g.n, g.lc, bid, g.a, g.da, 0u, g.scr, X);
+      else exec_col_dif<NT, RM, false>(pr, g.n, g.lc, bid - g.ntiles, g.b, g.db, pr.s2[g.n], g.scr + N, X);
       break;
-    case D_ROW_POLY: exec_row<NT, RM>(pr, kRowLog, ROW_POLY, g.scr + bid * S, g.scr + N + bid * S, 0u, X); break;
+    case D_ROW_POLY: exec_row<NT, RM, false>(pr, kRowLog, ROW_POLY, g.scr + bid * S, g.scr + N + bid * S, 0u, X); break;
     case D_COLI: exec_col_dit<NT, RM>(pr, g.n, g.lc, bid, g.scr, g.out, g.da + g.db + 1, X); break;
-    case D_FWD_SMALL: exec_row<NT, RM>(pr, g.n, ROW_FWD, g.out, nullptr, 0u, X); break;
-    case D_INV_SMALL: exec_row<NT, RM>(pr, g.n, ROW_INV, g.out, nullptr, g.prescale, X); break;
-    case D_COLF_INPLACE: exec_col_dif<NT, RM>(pr, g.n, g.lc, bid, g.out, N - 1, 0u, g.out, X); break;
-    case D_ROW_FWD: exec_row<NT, RM>(pr, kRowLog, ROW_FWD, g.out + bid * S, nullptr, 0u, X); break;
-    case D_ROW_INV: exec_row<NT, RM>(pr, kRowLog, ROW_INV, g.out + bid * S, nullptr, g.prescale, X); break;
+    case D_FWD_SMALL: exec_row<NT, RM, false>(pr, g.n, ROW_FWD, g.out, nullptr, 0u, X); break;
+    case D_INV_SMALL: exec_row<NT, RM, false>(pr, g.n, ROW_INV, g.out, nullptr, g.prescale, X); break;
+    case D_COLF_INPLACE: exec_col_dif<NT, RM, false>(pr, g.n, g.lc, bid, g.out, N - 1, 0u, g.out, X); break;
+    case D_ROW_FWD: exec_row<NT, RM, false>(pr, kRowLog, ROW_FWD, g.out + bid * S, nullptr, 0u, X); break;
+    case D_ROW_INV: exec_row<NT, RM, false>(pr, kRowLog, ROW_INV, g.out + bid * S, nullptr, g.prescale, X); break;
     default: exec_col_dit<NT, RM>(pr, g.n, g.lc, bid, g.out, g.out, N, X); break;
   }
 }
@@ -443,24 +463,20 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
         case T_SMALL:
           exec_small_poly<NT, RM>(pr, pd.n, g.in + pd.a_off, pd.da, g.in + pd.b_off, pd.db, g.out + pd.c_off, X);
           break;
-        case T_COLF_A: exec_col_dif<NT, RM>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X); break;
+        case T_COLF_A: exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X); break;
         case T_COLF_B:
-          exec_col_dif<NT, RM>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X);
+          exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X);
           break;
-        case T_ROW: exec_row<NT, RM>(pr, kRowLog, ROW_POLY, scr + idx * S, scr + N + idx * S, 0u, X); break;
+        case T_ROW: exec_row<NT, RM, true>(pr, kRowLog, ROW_POLY, scr + idx * S, scr + N + idx * S, 0u, X); break;
         default: exec_col_dit<NT, RM>(pr, pd.n, pd.lc, idx, scr, g.out + pd.c_off, pd.da + pd.db + 1, X); break;
       }
       if (kind != T_SMALL && kind != T_COLI) {
-        // Publish this task's stores at agent scope before counting it: every
-        // wave waits until its stores are in L2, then one lane writes the L2
-        // back (the release fence) so other XCDs can read the data, and only
-        // then bumps the product's counter.
+        // Publish: every wave waits until its coherent stores have completed,
+        // the workgroup meets, and one lane bumps the product's counter.
         __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
         if (threadIdx.x == 0) {
           uint32_t* ctr = kind == T_ROW ? cnt_row + p : cnt_col + p;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);      // the write-back has completed
           __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
