@@ -218,6 +218,135 @@ __device__ __forceinline__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uin
   }
 }
 
+// ---------------------------------------------------------------------------
+// The row pass of long transforms always covers LR = 13 stages of a
+// contiguous 2^13 block, so its rounds are generated at compile time: the
+// round geometry (first stage, group stride) is a constant, and the LDS
+// address of a group's j-th element needs at most one operation:
+//   * first stage >= 9: the swizzle touches only bits the stride never
+//     reaches, so lds_at(yb + j 2^s) = lds_at(yb) + j 2^s;
+//   * the group lies inside one 64-word row (first stage + R <= 6): the row
+//     key is shared, so lds_at(yb + j 2^s) = lds_at(yb) ^ (j 2^s);
+//   * otherwise the general lds_at.
+// The inverse uses the forward's round sizes in reverse order, so its first
+// rounds also fall in the cheap cases.
+// ---------------------------------------------------------------------------
+
+template <int LR, int RM>
+constexpr int fixed_nrounds() { return (LR + RM - 1) / RM; }
+
+template <int LR, int RM>
+constexpr int fixed_rsize(int idx) {
+  return LR / fixed_nrounds<LR, RM>() + (idx < LR % fixed_nrounds<LR, RM>() ? 1 : 0);
+}
+
+// First stage of forward round idx (rounds from the top).
+template <int LR, int RM>
+constexpr int fixed_dif_slo(int idx) {
+  int s = LR;
+  for (int i = 0; i <= idx; i++) s -= fixed_rsize<LR, RM>(i);
+  return s;
+}
+
+// Size and first stage of inverse round idx (sizes mirrored, from the bottom).
+template <int LR, int RM>
+constexpr int fixed_dit_rsize(int idx) { return fixed_rsize<LR, RM>(fixed_nrounds<LR, RM>() - 1 - idx); }
+
+template <int LR, int RM>
+constexpr int fixed_dit_slo(int idx) {
+  int s = 0;
+  for (int i = 0; i < idx; i++) s += fixed_dit_rsize<LR, RM>(i);
+  return s;
+}
+
+template <int A_LO, int R, int J>
+__device__ __forceinline__ uint32_t group_addr(uint32_t yb, uint32_t pb) {
+  constexpr uint32_t step = (uint32_t)J << A_LO;
+  if constexpr (A_LO >= 9) return pb + step;
+  else if constexpr (A_LO + R <= 6) return pb ^ step;
+  else return lds_at(yb + step);
+}
+
+template <int A_LO, int R, int J>
+__device__ __forceinline__ void fill_group_addr(uint32_t* ad, uint32_t yb, uint32_t pb) {
+  if constexpr (J < (1 << R)) {
+    ad[J] = group_addr<A_LO, R, J>(yb, pb);
+    fill_group_addr<A_LO, R, J + 1>(ad, yb, pb);
+  }
+}
+
+template <int NT, int NA, int R, bool INV, int LR, int S_LO>
+__device__ __forceinline__ void lds_round_row(uint32_t* X, int off, const uint32_t* tw, Mod md) {
+  constexpr int E = 1 << R;
+  constexpr uint32_t lomask = (1u << S_LO) - 1;
+  constexpr uint32_t ngroups = (1u << LR) >> R;
+  for (uint32_t g = threadIdx.x; g < ngroups; g += NT) {
+    const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
+    const uint32_t t0 = base & lomask;
+    uint32_t w[E - 1];
+#pragma unroll
+    for (int t = 0; t < R; t++)
+#pragma unroll
+      for (int jj = 0; jj < (1 << t); jj++)
+        w[(1 << t) - 1 + jj] = ldg(tw, (1u << (S_LO + t)) + t0 + ((uint32_t)jj << S_LO));
+#pragma nounroll
+    for (int a = 0; a < NA; a++) {
+      const uint32_t yb = (uint32_t)(a * off) + base;
+      const uint32_t pb = lds_at(yb);
+      uint32_t v[E];
+      uint32_t ad[E];
+      fill_group_addr<S_LO, R, 0>(ad, yb, pb);
+#pragma unroll
+      for (int j = 0; j < E; j++) v[j] = X[ad[j]];
+      if constexpr (!INV) {
+#pragma unroll
+        for (int t = R - 1; t >= 0; t--) {
+          const int d = 1 << t;
+#pragma unroll
+          for (int j = 0; j < E; j++) {
+            if (j & d) continue;
+            const uint32_t x = v[j], y = v[j + d];
+            v[j] = madd(x, y, md.P);
+            v[j + d] = mmul(x - y + md.P, w[d - 1 + (j & (d - 1))], md);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < R; t++) {
+          const int d = 1 << t;
+#pragma unroll
+          for (int j = 0; j < E; j++) {
+            if (j & d) continue;
+            const uint32_t x = v[j];
+            const uint32_t y = mmul(v[j + d], w[d - 1 + (j & (d - 1))], md);
+            v[j] = madd(x, y, md.P);
+            v[j + d] = msub(x, y, md.P);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < E; j++) X[ad[j]] = v[j];
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT, int NA, int RM, int LR, int IDX = 0>
+__device__ __forceinline__ void row_dif(uint32_t* X, int off, const uint32_t* tw, Mod md) {
+  if constexpr (IDX < fixed_nrounds<LR, RM>()) {
+    lds_round_row<NT, NA, fixed_rsize<LR, RM>(IDX), false, LR, fixed_dif_slo<LR, RM>(IDX)>(X, off, tw, md);
+    row_dif<NT, NA, RM, LR, IDX + 1>(X, off, tw, md);
+  }
+}
+
+template <int NT, int RM, int LR, int IDX = 0>
+__device__ __forceinline__ void row_dit(uint32_t* X, const uint32_t* tw, Mod md) {
+  if constexpr (IDX < fixed_nrounds<LR, RM>()) {
+    lds_round_row<NT, 1, fixed_dit_rsize<LR, RM>(IDX), true, LR, fixed_dit_slo<LR, RM>(IDX)>(X, 0, tw, md);
+    row_dit<NT, RM, LR, IDX + 1>(X, tw, md);
+  }
+}
+
 // Stores whose data another workgroup reads later in the same persistent
 // launch are agent-scope atomic stores (global_store ... sc1): they are
 // written through to the device coherence point, so a consumer on another
@@ -325,14 +454,16 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
   }
   __syncthreads();
   if (lr > 0) {
-    if (mode == ROW_POLY) lds_dif<NT, 2, RM>(X, (int)L, lr, 0, 0, 0, pr.twf, md);
+    if (mode == ROW_POLY && lr == kRowLog) row_dif<NT, 2, RM, kRowLog>(X, (int)L, pr.twf, md);
+    else if (mode == ROW_POLY) lds_dif<NT, 2, RM>(X, (int)L, lr, 0, 0, 0, pr.twf, md);
     else if (mode == ROW_FWD) lds_dif<NT, 1, RM>(X, 0, lr, 0, 0, 0, pr.twf, md);
   }
   if (mode == ROW_POLY) {
     for (uint32_t e = threadIdx.x; e < L; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(L + e)], md);
     __syncthreads();
   }
-  if (mode != ROW_FWD && lr > 0) lds_dit<NT, RM>(X, lr, 0, 0, 0, pr.twi, md);
+  if (mode != ROW_FWD && lr == kRowLog) row_dit<NT, RM, kRowLog>(X, pr.twi, md);
+  else if (mode != ROW_FWD && lr > 0) lds_dit<NT, RM>(X, lr, 0, 0, 0, pr.twi, md);
   for (uint32_t e = threadIdx.x; e < L; e += NT) st_out<COH>(gA + e, X[lds_at(e)]);
   __syncthreads();
 }
