@@ -76,8 +76,9 @@ MONT_API mont_status ntt_inverse(const ntt_ctx* ctx, int prime_id, uint32_t* d_x
  *   d_out[k] = sum_{i+j=k} d_a[i] d_b[j] mod P,  k = 0 .. da+db,
  * for d_a of da+1 and d_b of db+1 coefficients in [0, P).  The transform
  * length is N = 2^n, the least power of two >= da+db+1.  d_scratch must hold
- * ntt_polymul_scratch_bytes(da, db) bytes (0 when N <= 2^13, else 8N);
- * d_out must not overlap the inputs.  Errors: MONT_EINVAL, MONT_ERANGE
+ * ntt_polymul_scratch_bytes(da, db) bytes (0 when N <= 2^13, else 8N) and be
+ * 16-byte aligned (MONT_EINVAL otherwise); d_out must not overlap the inputs.
+ * Errors: MONT_EINVAL, MONT_ERANGE
  * (da+db+1 > 2^31), MONT_ENOROOT (N above the prime's table), MONT_ENOMEM
  * (scratch too small).
  */
@@ -152,7 +153,8 @@ MONT_API mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, 
  * hold the plan's scratch bytes; d_in and d_out the plan's word counts.  The
  * result is identical for every grid size and task order.  Enqueues two
  * kernels and no memset or allocation, so the call may be captured in a HIP
- * graph.  Calls that share a scratch buffer must not overlap.
+ * graph.  d_scratch must be 16-byte aligned (MONT_EINVAL otherwise).  Calls
+ * that share a scratch buffer must not overlap.
  */
 MONT_API mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_in, uint32_t* d_out, void* d_scratch,
                                       size_t scratch_bytes, int grid, uint32_t spin_limit, void* stream);

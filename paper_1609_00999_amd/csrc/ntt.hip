@@ -421,9 +421,22 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
   const uint32_t colbase = t << lc;
   const uint32_t cnt = 1u << (n1 + lc);
   const uint32_t cmask = (1u << lc) - 1;
-  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
-    const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
-    X[lds_at(e)] = src[i];
+  if (lc >= 2 && ((uintptr_t)src & 15u) == 0) {
+    // rows of C >= 4 adjacent residues: 128-bit loads
+    for (uint32_t e4 = threadIdx.x; e4 < (cnt >> 2); e4 += NT) {
+      const uint32_t e = e4 << 2;
+      const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+      const v4u v = *reinterpret_cast<const v4u*>(src + i);
+      X[lds_at(e)] = v.x;
+      X[lds_at(e + 1)] = v.y;
+      X[lds_at(e + 2)] = v.z;
+      X[lds_at(e + 3)] = v.w;
+    }
+  } else {
+    for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+      const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+      X[lds_at(e)] = src[i];
+    }
   }
   __syncthreads();
   lds_dit<NT, RM>(X, n1, lc, kRowLog, colbase, pr.twi, md);
@@ -446,11 +459,29 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
                          uint32_t prescale, uint32_t* X) {
   const Mod md = mod_of(pr);
   const uint32_t L = 1u << lr;
-  for (uint32_t e = threadIdx.x; e < L; e += NT) {
-    uint32_t v = gA[e];
-    if (mode == ROW_INV && prescale) v = mmul(v, prescale, md);
-    X[lds_at(e)] = v;
-    if (mode == ROW_POLY) X[lds_at(L + e)] = gB[e];
+  if (mode == ROW_POLY && lr >= 2 && (((uintptr_t)gA | (uintptr_t)gB) & 15u) == 0) {
+    // 128-bit loads of both blocks
+    const v4u* a4 = reinterpret_cast<const v4u*>(gA);
+    const v4u* b4 = reinterpret_cast<const v4u*>(gB);
+    for (uint32_t e4 = threadIdx.x; e4 < (L >> 2); e4 += NT) {
+      const v4u va = a4[e4], vb = b4[e4];
+      const uint32_t e = e4 << 2;
+      X[lds_at(e)] = va.x;
+      X[lds_at(e + 1)] = va.y;
+      X[lds_at(e + 2)] = va.z;
+      X[lds_at(e + 3)] = va.w;
+      X[lds_at(L + e)] = vb.x;
+      X[lds_at(L + e + 1)] = vb.y;
+      X[lds_at(L + e + 2)] = vb.z;
+      X[lds_at(L + e + 3)] = vb.w;
+    }
+  } else {
+    for (uint32_t e = threadIdx.x; e < L; e += NT) {
+      uint32_t v = gA[e];
+      if (mode == ROW_INV && prescale) v = mmul(v, prescale, md);
+      X[lds_at(e)] = v;
+      if (mode == ROW_POLY) X[lds_at(L + e)] = gB[e];
+    }
   }
   __syncthreads();
   if (lr > 0) {
@@ -1020,6 +1051,7 @@ extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint3
   if ((uint32_t)n > ctx->logmax[prime_id]) return MONT_ENOROOT;
   size_t need = ntt_polymul_scratch_bytes(da, db);
   if (need && (!d_scratch || scratch_bytes < need)) return MONT_ENOMEM;
+  if (need && !aligned16(d_scratch)) return MONT_EINVAL;
   hipStream_t s = as_stream(stream);
   (void)hipGetLastError();
   DirectArgs g = direct_base(ctx, prime_id, n);
@@ -1247,7 +1279,7 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   if (plan->count == 0) return MONT_OK;
   if (!d_in || !d_out || !d_scratch) return MONT_EINVAL;
   if (scratch_bytes < plan->scratch_words * 4) return MONT_ENOMEM;
-  if (grid < 0) return MONT_EINVAL;
+  if (grid < 0 || !aligned16(d_scratch)) return MONT_EINVAL;
   hipStream_t s = as_stream(stream);
   (void)hipGetLastError();
   uint32_t* scr = static_cast<uint32_t*>(d_scratch);
