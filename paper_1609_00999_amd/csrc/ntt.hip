@@ -396,11 +396,39 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
   const uint32_t colbase = t << lc;
   const uint32_t cnt = 1u << (n1 + lc);
   const uint32_t cmask = (1u << lc) - 1;
-  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
-    const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
-    uint32_t v = i <= dvalid ? src[i] : 0u;
-    if (scale) v = mmul(v, scale, md);
-    X[lds_at(e)] = v;
+  if (lc >= 2 && ((uintptr_t)src & 15u) == 0) {
+    // rows of C >= 4 adjacent residues: 128-bit loads where all four are
+    // inside the operand, element loads on the (at most one) straddling chunk
+    for (uint32_t e4 = threadIdx.x; e4 < (cnt >> 2); e4 += NT) {
+      const uint32_t e = e4 << 2;
+      const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+      v4u v;
+      if (i + 3 <= dvalid) {
+        v = *reinterpret_cast<const v4u*>(src + i);
+      } else {
+        v.x = i <= dvalid ? src[i] : 0u;
+        v.y = i + 1 <= dvalid ? src[i + 1] : 0u;
+        v.z = i + 2 <= dvalid ? src[i + 2] : 0u;
+        v.w = 0u;
+      }
+      if (scale) {
+        v.x = mmul(v.x, scale, md);
+        v.y = mmul(v.y, scale, md);
+        v.z = mmul(v.z, scale, md);
+        v.w = mmul(v.w, scale, md);
+      }
+      X[lds_at(e)] = v.x;
+      X[lds_at(e + 1)] = v.y;
+      X[lds_at(e + 2)] = v.z;
+      X[lds_at(e + 3)] = v.w;
+    }
+  } else {
+    for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+      const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
+      uint32_t v = i <= dvalid ? src[i] : 0u;
+      if (scale) v = mmul(v, scale, md);
+      X[lds_at(e)] = v;
+    }
   }
   __syncthreads();
   lds_dif<NT, 1, RM>(X, 0, n1, lc, kRowLog, colbase, pr.twf, md);

@@ -99,17 +99,18 @@ def pack_products(primes, prime_id, da, db, rng: np.random.Generator) -> Polymul
     pos = 0
     cpos = 0
     for i in range(count):
-        a_off[i] = pos
-        pos += int(la[i])
+        a_off[i] = pos                       # every operand starts on a 16-byte boundary
+        pos += (int(la[i]) + 3) & ~3
         b_off[i] = pos
-        pos += int(lb[i])
+        pos += (int(lb[i]) + 3) & ~3
         c_off[i] = cpos
         cpos += int(la[i] + lb[i] - 1)
-    coeffs = np.empty(pos, dtype=np.uint32)
+    coeffs = np.zeros(pos, dtype=np.uint32)
     for i in range(count):
         P = primes[int(prime_id[i])]
-        n = int(la[i] + lb[i])
-        coeffs[a_off[i]: a_off[i] + n] = uniform(rng, 0, P, n)
+        vals = uniform(rng, 0, P, int(la[i] + lb[i]))
+        coeffs[a_off[i]: a_off[i] + la[i]] = vals[:la[i]]
+        coeffs[b_off[i]: b_off[i] + lb[i]] = vals[la[i]:]
     return PolymulBatch(tuple(primes), prime_id, da, db, a_off, b_off, c_off, coeffs, cpos)
 
 

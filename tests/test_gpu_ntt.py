@@ -322,3 +322,47 @@ def test_batch_graph_replay(N, ctx):
         assert np.array_equal(host(out), eager), r
     del g
     plan.close()
+
+
+@pytest.mark.parametrize("off", [1, 2, 3])
+def test_polymul_misaligned_operands(N, ctx, off):
+    """Operands that do not start on a 16-byte boundary take the element-load path."""
+    P = PRIMES[off]
+    rng = np.random.default_rng(100 + off)
+    da, db = 9000 + off, 7000 - off
+    a = rng.integers(0, P, da + 1 + off, dtype=np.uint32)
+    b = rng.integers(0, P, db + 1 + off, dtype=np.uint32)
+    out = torch.zeros(da + db + 1 + off, dtype=torch.int32, device="cuda")[off:]
+    got = host(N.polymul(ctx, off, dev(a)[off:], dev(b)[off:], out=out))
+    assert np.array_equal(got, oracle.polymul(P, a[off:], b[off:]))
+
+
+def test_batch_unaligned_offsets(N, ctx):
+    """A hand-packed batch whose operands sit at odd offsets."""
+    rng = np.random.default_rng(46)
+    da = np.array([5000, 20000, 3, 17000, 70000])
+    db = np.array([6000, 19999, 9000, 2, 65000])
+    pid = np.array([0, 3, 5, 7, 1])
+    a_off, b_off, c_off, pos, cpos = [], [], [], 1, 0
+    for x, y in zip(da, db):
+        a_off.append(pos)
+        pos += int(x) + 2
+        b_off.append(pos)
+        pos += int(y) + 1
+        c_off.append(cpos)
+        cpos += int(x + y + 1)
+    coeffs = np.zeros(pos, dtype=np.uint32)
+    for i in range(da.size):
+        P = PRIMES[pid[i]]
+        coeffs[a_off[i]: a_off[i] + da[i] + 1] = rng.integers(0, P, da[i] + 1, dtype=np.uint32)
+        coeffs[b_off[i]: b_off[i] + db[i] + 1] = rng.integers(0, P, db[i] + 1, dtype=np.uint32)
+    plan = N.Plan(ctx, pid, da, db, a_off, b_off, c_off)
+    out = torch.zeros(cpos, dtype=torch.int32, device="cuda")
+    scr = plan.alloc_scratch()
+    plan.execute(dev(coeffs), out, scr)
+    assert plan.status(scr) == 0
+    got = host(out)
+    for i in range(da.size):
+        P = PRIMES[pid[i]]
+        ref = oracle.polymul(P, coeffs[a_off[i]: a_off[i] + da[i] + 1], coeffs[b_off[i]: b_off[i] + db[i] + 1])
+        assert np.array_equal(got[c_off[i]: c_off[i] + ref.size], ref), i
