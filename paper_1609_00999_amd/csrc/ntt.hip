@@ -275,27 +275,33 @@ __device__ __forceinline__ void fill_group_addr(uint32_t* ad, uint32_t yb, uint3
   }
 }
 
-template <int NT, int NA, int R, bool INV, int LR, int S_LO>
-__device__ __forceinline__ void lds_round_row(uint32_t* X, int off, const uint32_t* tw, Mod md) {
+// One round with compile-time geometry: rows of 2^LC columns (LC = 0 for the
+// row pass), transform length 2^LR along rows, global row stride 2^RS.
+template <int NT, int NA, int R, bool INV, int LR, int LC, int RS, int S_LO>
+__device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t colbase, const uint32_t* tw,
+                                                Mod md) {
   constexpr int E = 1 << R;
-  constexpr uint32_t lomask = (1u << S_LO) - 1;
-  constexpr uint32_t ngroups = (1u << LR) >> R;
+  constexpr int A_LO = S_LO + LC;
+  constexpr uint32_t lomask = (1u << A_LO) - 1;
+  constexpr uint32_t ngroups = (1u << (LR + LC)) >> R;
   for (uint32_t g = threadIdx.x; g < ngroups; g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
-    const uint32_t t0 = base & lomask;
+    const uint32_t c = base & ((1u << LC) - 1);
+    const uint32_t t0 = colbase + c + (((base >> LC) & ((1u << S_LO) - 1)) << RS);
+    const uint32_t* twg = tw + t0;
     uint32_t w[E - 1];
 #pragma unroll
     for (int t = 0; t < R; t++)
 #pragma unroll
       for (int jj = 0; jj < (1 << t); jj++)
-        w[(1 << t) - 1 + jj] = ldg(tw, (1u << (S_LO + t)) + t0 + ((uint32_t)jj << S_LO));
+        w[(1 << t) - 1 + jj] = ldg(twg, (1u << (S_LO + t + RS)) + ((uint32_t)jj << (S_LO + RS)));
 #pragma nounroll
     for (int a = 0; a < NA; a++) {
       const uint32_t yb = (uint32_t)(a * off) + base;
       const uint32_t pb = lds_at(yb);
       uint32_t v[E];
       uint32_t ad[E];
-      fill_group_addr<S_LO, R, 0>(ad, yb, pb);
+      fill_group_addr<A_LO, R, 0>(ad, yb, pb);
 #pragma unroll
       for (int j = 0; j < E; j++) v[j] = X[ad[j]];
       if constexpr (!INV) {
@@ -331,19 +337,54 @@ __device__ __forceinline__ void lds_round_row(uint32_t* X, int off, const uint32
   __syncthreads();
 }
 
-template <int NT, int NA, int RM, int LR, int IDX = 0>
-__device__ __forceinline__ void row_dif(uint32_t* X, int off, const uint32_t* tw, Mod md) {
+template <int NT, int NA, int RM, int LR, int LC, int RS, int IDX = 0>
+__device__ __forceinline__ void fixed_dif(uint32_t* X, int off, uint32_t colbase, const uint32_t* tw, Mod md) {
   if constexpr (IDX < fixed_nrounds<LR, RM>()) {
-    lds_round_row<NT, NA, fixed_rsize<LR, RM>(IDX), false, LR, fixed_dif_slo<LR, RM>(IDX)>(X, off, tw, md);
-    row_dif<NT, NA, RM, LR, IDX + 1>(X, off, tw, md);
+    lds_round_fixed<NT, NA, fixed_rsize<LR, RM>(IDX), false, LR, LC, RS, fixed_dif_slo<LR, RM>(IDX)>(X, off, colbase,
+                                                                                                     tw, md);
+    fixed_dif<NT, NA, RM, LR, LC, RS, IDX + 1>(X, off, colbase, tw, md);
   }
 }
 
-template <int NT, int RM, int LR, int IDX = 0>
-__device__ __forceinline__ void row_dit(uint32_t* X, const uint32_t* tw, Mod md) {
+template <int NT, int RM, int LR, int LC, int RS, int IDX = 0>
+__device__ __forceinline__ void fixed_dit(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
   if constexpr (IDX < fixed_nrounds<LR, RM>()) {
-    lds_round_row<NT, 1, fixed_dit_rsize<LR, RM>(IDX), true, LR, fixed_dit_slo<LR, RM>(IDX)>(X, 0, tw, md);
-    row_dit<NT, RM, LR, IDX + 1>(X, tw, md);
+    lds_round_fixed<NT, 1, fixed_dit_rsize<LR, RM>(IDX), true, LR, LC, RS, fixed_dit_slo<LR, RM>(IDX)>(X, 0, colbase,
+                                                                                                       tw, md);
+    fixed_dit<NT, RM, LR, LC, RS, IDX + 1>(X, colbase, tw, md);
+  }
+}
+
+// Column tiles of a length-2^N transform: 2^(N-13) rows x 2^col_lc(N) columns.
+
+constexpr int col_lc_c(int n) { return 13 < 14 - (n - 13) ? 13 : 14 - (n - 13); }
+
+template <int NT, int RM, int N>
+__device__ __forceinline__ void col_dif_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+  fixed_dif<NT, 1, RM, N - 13, col_lc_c(N), 13>(X, 0, colbase, tw, md);
+}
+
+template <int NT, int RM, int N>
+__device__ __forceinline__ void col_dit_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+  fixed_dit<NT, RM, N - 13, col_lc_c(N), 13>(X, colbase, tw, md);
+}
+
+// Column stages for length 2^n: compile-time rounds for 14 <= n <= 23, the
+// general rounds otherwise.
+template <int NT, int RM, bool INV>
+__device__ __forceinline__ void col_stages(int n, int lc, uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+  switch (n) {
+#define MONT_COL(NN)                                                 \
+  case NN:                                                           \
+    if constexpr (INV) col_dit_fixed<NT, RM, NN>(X, colbase, tw, md); \
+    else col_dif_fixed<NT, RM, NN>(X, colbase, tw, md);              \
+    return;
+    MONT_COL(14) MONT_COL(15) MONT_COL(16) MONT_COL(17) MONT_COL(18)
+    MONT_COL(19) MONT_COL(20) MONT_COL(21) MONT_COL(22) MONT_COL(23)
+#undef MONT_COL
+    default:
+      if constexpr (INV) lds_dit<NT, RM>(X, n - kRowLog, lc, kRowLog, colbase, tw, md);
+      else lds_dif<NT, 1, RM>(X, 0, n - kRowLog, lc, kRowLog, colbase, tw, md);
   }
 }
 
@@ -431,7 +472,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
     }
   }
   __syncthreads();
-  lds_dif<NT, 1, RM>(X, 0, n1, lc, kRowLog, colbase, pr.twf, md);
+  col_stages<NT, RM, false>(n, lc, X, colbase, pr.twf, md);
   for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     st_out<COH>(dst + i, X[lds_at(e)]);
@@ -467,7 +508,7 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
     }
   }
   __syncthreads();
-  lds_dit<NT, RM>(X, n1, lc, kRowLog, colbase, pr.twi, md);
+  col_stages<NT, RM, true>(n, lc, X, colbase, pr.twi, md);
   for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     if (i < nout) dst[i] = X[lds_at(e)];
@@ -513,7 +554,7 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
   }
   __syncthreads();
   if (lr > 0) {
-    if (mode == ROW_POLY && lr == kRowLog) row_dif<NT, 2, RM, kRowLog>(X, (int)L, pr.twf, md);
+    if (mode == ROW_POLY && lr == kRowLog) fixed_dif<NT, 2, RM, kRowLog, 0, 0>(X, (int)L, 0u, pr.twf, md);
     else if (mode == ROW_POLY) lds_dif<NT, 2, RM>(X, (int)L, lr, 0, 0, 0, pr.twf, md);
     else if (mode == ROW_FWD) lds_dif<NT, 1, RM>(X, 0, lr, 0, 0, 0, pr.twf, md);
   }
@@ -521,7 +562,7 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
     for (uint32_t e = threadIdx.x; e < L; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(L + e)], md);
     __syncthreads();
   }
-  if (mode != ROW_FWD && lr == kRowLog) row_dit<NT, RM, kRowLog>(X, pr.twi, md);
+  if (mode != ROW_FWD && lr == kRowLog) fixed_dit<NT, RM, kRowLog, 0, 0>(X, 0u, pr.twi, md);
   else if (mode != ROW_FWD && lr > 0) lds_dit<NT, RM>(X, lr, 0, 0, 0, pr.twi, md);
   for (uint32_t e = threadIdx.x; e < L; e += NT) st_out<COH>(gA + e, X[lds_at(e)]);
   __syncthreads();
