@@ -157,7 +157,7 @@ MONT_API mont_status mont_batch_destroy(mont_batch* b);
 /*
  * Launch-shape tuning of the streaming elementwise kernels (used by the
  * autotuner).  op: 0 = to, 1 = from, 2 = mul, 3 = muladd, 4 = pow.  block is
- * 256 or 512 threads, vpt 1, 2 or 4 128-bit vectors per thread, nontemporal
+ * 64, 128, 256 or 512 threads, vpt 1, 2 or 4 128-bit vectors per thread, nontemporal
  * 0 or 1.  Settings are process-wide and take effect on the next call; they
  * never change results.  Returns MONT_EINVAL for values outside those sets.
  */

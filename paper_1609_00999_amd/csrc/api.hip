@@ -46,7 +46,8 @@ extern "C" mont_status mont_setup(uint32_t P, mont_params* out) {
 
 extern "C" mont_status mont_elem_tune_set(int op, int block, int vpt, int nontemporal) {
   if (op < 0 || op >= mont::OP_COUNT) return MONT_EINVAL;
-  if ((block != 256 && block != 512) || (vpt != 1 && vpt != 2 && vpt != 4)) return MONT_EINVAL;
+  if ((block != 64 && block != 128 && block != 256 && block != 512) || (vpt != 1 && vpt != 2 && vpt != 4))
+    return MONT_EINVAL;
   mont::elem_tune(op) = mont::ElemTune{block, vpt, nontemporal ? 1 : 0};
   return MONT_OK;
 }

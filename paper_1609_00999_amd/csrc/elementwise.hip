@@ -166,8 +166,12 @@ void dispatch(const ElemTune& t, Mod md, uint32_t kc, const uint32_t* a, const u
     launch_v4<OP, B, V, N>(md, kc, a, b, c, out, n, s);           \
     return;                                                       \
   }
+  MONT_CASE(64, 1, true) MONT_CASE(64, 2, true) MONT_CASE(64, 4, true)
+  MONT_CASE(128, 1, true) MONT_CASE(128, 2, true) MONT_CASE(128, 4, true)
   MONT_CASE(256, 1, true) MONT_CASE(256, 2, true) MONT_CASE(256, 4, true)
   MONT_CASE(512, 1, true) MONT_CASE(512, 2, true) MONT_CASE(512, 4, true)
+  MONT_CASE(64, 1, false) MONT_CASE(64, 2, false) MONT_CASE(64, 4, false)
+  MONT_CASE(128, 1, false) MONT_CASE(128, 2, false) MONT_CASE(128, 4, false)
   MONT_CASE(256, 1, false) MONT_CASE(256, 2, false) MONT_CASE(256, 4, false)
   MONT_CASE(512, 1, false) MONT_CASE(512, 2, false) MONT_CASE(512, 4, false)
 #undef MONT_CASE

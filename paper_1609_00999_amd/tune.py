@@ -9,7 +9,7 @@ tests check every shape against the oracle).
 
 Tuned knobs:
   * elementwise (per op: to, from, mul, muladd, pow): threads per workgroup
-    {256, 512} x 128-bit vectors per lane {1, 2, 4} x non-temporal {0, 1};
+    {64, 128, 256, 512} x 128-bit vectors per lane {1, 2, 4} x non-temporal {0, 1};
   * transforms (one setting for all transform kernels): threads per
     workgroup {256, 512, 1024} x largest register round {3, 4} stages, and
     the persistent grid as a multiple of the resident workgroup count.
@@ -28,7 +28,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(PKG, "tune_cache.json")
 
-ELEM_SHAPES = [(b, v, nt) for b in (256, 512) for v in (1, 2, 4) for nt in (1, 0)]
+ELEM_SHAPES = [(b, v, nt) for b in (64, 128, 256, 512) for v in (1, 2, 4) for nt in (1, 0)]
 NTT_SHAPES = [(t, r) for t in (256, 512, 1024) for r in (3, 4)]
 GRID_MULTS = (1, 2)
 applied: dict = {}

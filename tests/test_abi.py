@@ -90,7 +90,7 @@ def test_elem_tune(L):
         mont.elem_tune_set("mul", 512, 2, False)
         assert mont.elem_tune_get("mul") == (512, 2, False)
         with pytest.raises(mont.MontError):
-            mont.elem_tune_set("mul", 128, 2, False)
+            mont.elem_tune_set("mul", 96, 2, False)
         assert L.mont_elem_tune_set(9, 256, 1, 1) == -1
     finally:
         mont.elem_tune_set("mul", *old)
