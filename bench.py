@@ -254,7 +254,27 @@ def extras(torch, mont, wl, dev):
     out["pow_n2^24"] = {"ms": round(s * 1e3, 4), "pow_per_s": round(e.size / s, 1),
                         "Gmodmul_per_s_algorithmic": round(alg / s / 1e9, 2),
                         "Gredc_per_s_executed": round(executed / s / 1e9, 2)}
-    del dbase, dexp, dout
+    # The paper's three reductions on the same operands: Algorithm 2 (the
+    # product path), Algorithm 3 (Fourier-prime REDC) and Algorithm 1 (Barrett
+    # on ordinary residues).  pow is ALU-bound: 47 reductions per element.
+    alg = {}
+    for name, fn in (("alg2_montgomery", lambda: mont.pow(prm, dbase, dexp, out=dout)),
+                     ("alg3_fourier", lambda: mont.pow_fourier(prm, dbase, dexp, out=dout)),
+                     ("alg1_barrett", lambda: mont.pow_barrett(P, dbase, dexp, out=dout))):
+        s = timed(torch, fn, 10)
+        alg[name] = {"pow_ms": round(s * 1e3, 4), "Gredc_per_s": round(executed / s / 1e9, 1)}
+    n = 1 << 28
+    xa = torch.randint(0, P, (n,), dtype=torch.int32, device=dev)
+    xb = torch.randint(0, P, (n,), dtype=torch.int32, device=dev)
+    xo = torch.empty_like(xa)
+    for name, fn in (("alg2_montgomery", lambda: mont.mul(prm, xa, xb, out=xo)),
+                     ("alg3_fourier", lambda: mont.mul_fourier(prm, xa, xb, out=xo)),
+                     ("alg1_barrett", lambda: mont.mul_barrett(P, xa, xb, out=xo))):
+        s = timed(torch, fn, 10)
+        alg[name]["mul_n2^28_us"] = round(s * 1e6, 1)
+        alg[name]["mul_GB_per_s"] = round(12 * n / s / 1e9, 1)
+    out["reductions_P998244353"] = alg
+    del dbase, dexp, dout, xa, xb, xo
     out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
     out["serving"] = serving_extra(torch, wl, dev)
     return out

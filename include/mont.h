@@ -116,6 +116,38 @@ MONT_API mont_status mont_pow(const mont_params* prm, const uint32_t* d_base, co
                      size_t n, void* stream);
 
 /*
+ * The paper's other two modular multiplications, for comparison with
+ * Algorithm 2 (section 3.1).
+ *
+ * mont_mul_fourier / mont_pow_fourier -- Algorithm 3 (REDC for a Fourier
+ * prime P = c 2^k + 1 with 2k >= 32, i.e. prm->k >= 16): with K = c 2^k = P-1
+ * and T = a*b = q1 R + r1, K r1 = q2 R + r2 and q3 = floor(K r2 / R), the
+ * result is q1 - q2 + q3 reduced into [0, P).  The paper's corrections use an
+ * arithmetic shift of a signed 32-bit sum in (-(P-1), 2(P-1)), which
+ * overflows once P > 2^30; these kernels take the sign from an explicit
+ * borrow instead, so they are exact for every 31-bit Fourier prime.  Same
+ * operands, results and contracts as mont_mul / mont_pow (residues in and
+ * out).  MONT_EINVAL if prm->k < 16.
+ */
+MONT_API mont_status mont_mul_fourier(const mont_params* prm, const uint32_t* d_a, const uint32_t* d_b,
+                                      uint32_t* d_out, size_t n, void* stream);
+MONT_API mont_status mont_pow_fourier(const mont_params* prm, const uint32_t* d_base, const uint32_t* d_exp,
+                                      uint32_t* d_out, size_t n, void* stream);
+
+/*
+ * modmul_barrett / modpow_barrett -- Algorithm 1 (Barrett) on ORDINARY
+ * residues (no Montgomery form): d_out[i] = d_a[i]*d_b[i] mod P, respectively
+ * d_base[i]^d_exp[i] mod P (0^0 = 1).  With k the bit length of P and
+ * P' = floor(2^(2k) / P): m = floor(ab / 2^k), q = floor(m P' / 2^k),
+ * t = ab - qP < 4P, at most three subtractions.  Odd 3 <= P < 2^31; operands
+ * in [0, P).  MONT_EINVAL for an invalid P.
+ */
+MONT_API mont_status modmul_barrett(uint32_t P, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out, size_t n,
+                                    void* stream);
+MONT_API mont_status modpow_barrett(uint32_t P, const uint32_t* d_base, const uint32_t* d_exp, uint32_t* d_out,
+                                    size_t n, void* stream);
+
+/*
  * Batches of vectors.  One descriptor per vector: device pointers a, b, out
  * (n residues each, out may equal a or b), and the vector's own modulus P
  * with P' = -P^-1 mod 2^32 as mont_setup returns them.

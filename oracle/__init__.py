@@ -56,6 +56,8 @@ def _load():
     lib.orc_mul.argtypes = [u32, u32, _u32p, _u32p, _u32p, sz]
     lib.orc_muladd.argtypes = [u32, u32, _u32p, _u32p, _u32p, _u32p, sz]
     lib.orc_pow.argtypes = [u32, ctypes.c_int, u32, _u32p, _u32p, _u32p, sz]
+    lib.orc_modmul.argtypes = [u32, _u32p, _u32p, _u32p, sz]
+    lib.orc_modpow.argtypes = [u32, _u32p, _u32p, _u32p, sz]
     lib.orc_polymul_schoolbook.argtypes = [u32, _u32p, u32, _u32p, u32, _u32p]
     lib.orc_horner.argtypes = [u32, _u32p, u32, u32]
     lib.orc_horner.restype = u32
@@ -174,6 +176,29 @@ def mont_pow(P: int, base, exp, r: int = 32, threads: int | None = None) -> np.n
     lib = _load()
     _run_chunked(lambda s, e: lib.orc_pow(P, r, prm.Rinv, _p(base[s:e]), _p(exp[s:e]), _p(out[s:e]),
                                           e - s), base.size, threads)
+    return out
+
+
+def modmul(P: int, a, b, threads: int | None = None) -> np.ndarray:
+    """Ordinary a*b mod P."""
+    a, b = _u32(a), _u32(b)
+    if a.shape != b.shape:
+        raise ValueError("shape mismatch")
+    out = np.empty_like(a)
+    lib = _load()
+    _run_chunked(lambda s, e: lib.orc_modmul(P, _p(a[s:e]), _p(b[s:e]), _p(out[s:e]), e - s), a.size, threads)
+    return out
+
+
+def modpow(P: int, base, exp, threads: int | None = None) -> np.ndarray:
+    """Ordinary a^e mod P (0^0 = 1)."""
+    base, exp = _u32(base), _u32(exp)
+    if base.shape != exp.shape:
+        raise ValueError("shape mismatch")
+    out = np.empty_like(base)
+    lib = _load()
+    _run_chunked(lambda s, e: lib.orc_modpow(P, _p(base[s:e]), _p(exp[s:e]), _p(out[s:e]), e - s), base.size,
+                 threads)
     return out
 
 

@@ -244,3 +244,13 @@ int orc_polymul_ntt(uint32_t P, uint32_t g, const uint32_t* a, uint32_t da, cons
   for (uint64_t k = 0; k < need; k++) c[k] = mulmod(A[k], ninv, P);
   return 0;
 }
+
+/* Ordinary modular product a*b mod P and power a^e mod P (no residue
+ * representation): the results Algorithm 1 (Barrett) must reproduce. */
+void orc_modmul(uint32_t P, const uint32_t* a, const uint32_t* b, uint32_t* out, size_t n) {
+  for (size_t i = 0; i < n; i++) out[i] = mulmod(a[i] % P, b[i] % P, P);
+}
+
+void orc_modpow(uint32_t P, const uint32_t* base, const uint32_t* e, uint32_t* out, size_t n) {
+  for (size_t i = 0; i < n; i++) out[i] = powmod(base[i], e[i], P);
+}

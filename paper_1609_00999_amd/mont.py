@@ -53,6 +53,10 @@ def lib() -> ctypes.CDLL:
     for name in ("mont_mul", "mont_pow"):
         getattr(L, name).argtypes = [pp, c_vp, c_vp, c_vp, c_size, c_vp]
     L.mont_muladd.argtypes = [pp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]
+    for name in ("mont_mul_fourier", "mont_pow_fourier"):
+        getattr(L, name).argtypes = [pp, c_vp, c_vp, c_vp, c_size, c_vp]
+    for name in ("modmul_barrett", "modpow_barrett"):
+        getattr(L, name).argtypes = [c_u32, c_vp, c_vp, c_vp, c_size, c_vp]
     L.mont_batch_reserve.argtypes = [ctypes.c_int, ctypes.POINTER(c_vp)]
     L.mont_batch_update.argtypes = [c_vp, c_vp, ctypes.c_int, c_vp]
     L.mont_batch_mul.argtypes = [c_vp, c_vp]
@@ -194,6 +198,37 @@ def pow(prm: MontParams, base, exp, out=None):  # noqa: A001 - mirrors mont_pow
     check(lib().mont_pow(ctypes.byref(prm), dev_ptr(base, "base"), dev_ptr(exp, "exp"), dev_ptr(out, "out"),
                          base.numel(), stream_handle()), "mont_pow")
     return out
+
+
+def _binary(fn, first, a, b, out, name):
+    if a.numel() != b.numel():
+        raise ValueError("operand sizes differ")
+    if out is None:
+        out = empty_like_u32(a)
+    if out.numel() != a.numel():
+        raise ValueError("out size differs")
+    check(fn(first, dev_ptr(a, "a"), dev_ptr(b, "b"), dev_ptr(out, "out"), a.numel(), stream_handle()), name)
+    return out
+
+
+def mul_fourier(prm: MontParams, a, b, out=None):
+    """Algorithm 3 (Fourier-prime REDC) elementwise; same result as mul()."""
+    return _binary(lib().mont_mul_fourier, ctypes.byref(prm), a, b, out, "mont_mul_fourier")
+
+
+def pow_fourier(prm: MontParams, base, exp, out=None):
+    """pow() with Algorithm 3 in place of Algorithm 2; same result."""
+    return _binary(lib().mont_pow_fourier, ctypes.byref(prm), base, exp, out, "mont_pow_fourier")
+
+
+def mul_barrett(P: int, a, b, out=None):
+    """Algorithm 1 (Barrett) on ordinary residues: a*b mod P."""
+    return _binary(lib().modmul_barrett, P, a, b, out, "modmul_barrett")
+
+
+def pow_barrett(P: int, base, exp, out=None):
+    """Ordinary a^e mod P with Algorithm 1 products."""
+    return _binary(lib().modpow_barrett, P, base, exp, out, "modpow_barrett")
 
 
 class VecDesc(ctypes.Structure):

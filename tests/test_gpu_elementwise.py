@@ -196,3 +196,44 @@ def test_exhaustive_tiny_modulus(M):
         a, b = a.ravel().copy(), b.ravel().copy()
         assert np.array_equal(host(M.mul(prm, dev(a), dev(b))), oracle.mont_mul(P, a, b))
         assert np.array_equal(host(M.pow(prm, dev(a), dev(b))), oracle.mont_pow(P, a, b))
+
+
+@pytest.mark.parametrize("P", sorted(set(wl.PRIMES_BW) | set(wl.PRIMES_NTT)))
+def test_fourier_redc_matches_alg2(M, P):
+    """Algorithm 3 (Fourier-prime REDC, borrow form) gives Algorithm 2's results."""
+    prm = M.setup(P)
+    rng = np.random.default_rng(P % 7919)
+    e = edge_values(P)
+    a = np.concatenate([np.repeat(e, e.size), rng.integers(0, P, 100003, dtype=np.uint32)])
+    b = np.concatenate([np.tile(e, e.size), rng.integers(0, P, a.size - e.size * e.size, dtype=np.uint32)])
+    da, db = dev(a), dev(b)
+    assert np.array_equal(host(M.mul_fourier(prm, da, db)), oracle.mont_mul(P, a, b))
+    ex = rng.integers(0, 1 << 32, a.size, dtype=np.uint64).astype(np.uint32)
+    assert np.array_equal(host(M.pow_fourier(prm, da, dev(ex))), oracle.mont_pow(P, a, ex))
+    assert np.array_equal(host(M.pow_fourier(prm, da, dev(ex))), host(M.pow(prm, da, dev(ex))))
+
+
+@pytest.mark.parametrize("P", [3, 17, 65537, 1000003, 2147483647] + list(wl.PRIMES_BW))
+def test_barrett_matches_plain(M, P):
+    """Algorithm 1 (Barrett) on ordinary residues against the plain product."""
+    rng = np.random.default_rng(P % 6007)
+    n = 50001
+    a = rng.integers(0, P, n, dtype=np.uint32)
+    b = rng.integers(0, P, n, dtype=np.uint32)
+    a[:4] = [0, 1, P - 1, P - 1]
+    b[:4] = [P - 1, P - 1, P - 1, 1]
+    da, db = dev(a), dev(b)
+    assert np.array_equal(host(M.mul_barrett(P, da, db)), oracle.modmul(P, a, b))
+    ex = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    assert np.array_equal(host(M.pow_barrett(P, da, dev(ex))), oracle.modpow(P, a, ex))
+
+
+def test_alt_reduction_errors(M):
+    prm = M.setup(2013265921)
+    x = dev(np.ones(8, dtype=np.uint32))
+    with pytest.raises(M.MontError):
+        M.mul_fourier(M.setup(17), x, x)        # v2(16) = 4 < 16: not a usable Fourier prime
+    with pytest.raises(M.MontError):
+        M.mul_barrett(10, x, x)
+    assert np.array_equal(host(M.mul_fourier(prm, x[1:], x[1:])), oracle.mont_mul(2013265921, np.ones(7, np.uint32),
+                                                                                 np.ones(7, np.uint32)))
