@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--n-log2", type=int, default=28, help="elements per array (default 2^28)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip side measurements of other rows")
+    ap.add_argument("--extras-only", default=None,
+                    help="comma list out of %s: run only these side measurements, print them as one "
+                         "JSON object and skip the headline step (for profiling runs)" % ",".join(EXTRAS))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2^28-element int32 copy kernel (bitwise_not) three times, "
                          "whose HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
@@ -75,6 +78,13 @@ def main():
     mont.lib()
     dev = torch.device("cuda:0")
     n = 1 << args.n_log2
+    if args.extras_only:
+        which = tuple(x.strip() for x in args.extras_only.split(",") if x.strip())
+        bad = [x for x in which if x not in EXTRAS]
+        if bad:
+            raise SystemExit("unknown extras: %s (choose from %s)" % (bad, ", ".join(EXTRAS)))
+        print(json.dumps({"extras": extras(torch, mont, wl, dev, which)}), flush=True)
+        return
 
     # ---------------- inputs, resident in HBM ----------------
     t0 = time.time()
@@ -222,9 +232,29 @@ def timed(torch, fn, reps=5):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-def extras(torch, mont, wl, dev):
-    """Side measurements: the n = 2^20 to/mul/from pipeline and mont_pow."""
+EXTRAS = ("pipeline", "pow", "reductions", "polymul", "serving")
+
+
+def extras(torch, mont, wl, dev, which=EXTRAS):
+    """Side measurements of the other rows, by name (EXTRAS)."""
     out = {}
+    if "pipeline" in which:
+        out["plain_pipeline_n2^20"] = pipeline_extra(torch, mont, wl, dev)
+    if "pow" in which or "reductions" in which:
+        pw, red = pow_extras(torch, mont, wl, dev, "reductions" in which)
+        if "pow" in which:
+            out["pow_n2^24"] = pw
+        if red is not None:
+            out["reductions_P998244353"] = red
+    if "polymul" in which:
+        out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
+    if "serving" in which:
+        out["serving"] = serving_extra(torch, wl, dev)
+    return out
+
+
+def pipeline_extra(torch, mont, wl, dev):
+    """n = 2^20 pairs: to, to, mul, from (a*b mod P from ordinary operands)."""
     P = wl.P_PLAIN
     prm = mont.setup(P)
     a, b = wl.plain_pairs()
@@ -238,8 +268,14 @@ def extras(torch, mont, wl, dev):
         mont.mul(prm, ta, tb, out=tc)
         mont.from_mont(prm, tc, out=tc)
     s = timed(torch, pipe, 50)
-    out["plain_pipeline_n2^20"] = {"us": round(s * 1e6, 2), "Gmodmul_per_s": round(a.size / s / 1e9, 2)}
+    return {"us": round(s * 1e6, 2), "Gmodmul_per_s": round(a.size / s / 1e9, 2)}
 
+
+def pow_extras(torch, mont, wl, dev, reductions):
+    """mont_pow at n = 2^24, and optionally the paper's three reductions on
+    the same operands: Algorithm 2 (the product path), Algorithm 3
+    (Fourier-prime REDC) and Algorithm 1 (Barrett on ordinary residues).
+    pow is ALU-bound (47 reductions per element); mul is HBM-bound."""
     P = wl.P_POW
     prm = mont.setup(P)
     base, e = wl.pow_inputs()
@@ -251,18 +287,18 @@ def extras(torch, mont, wl, dev):
     pc = int(np.unpackbits(e.view(np.uint8)).sum())
     alg = 31 * e.size + pc
     executed = 47 * e.size
-    out["pow_n2^24"] = {"ms": round(s * 1e3, 4), "pow_per_s": round(e.size / s, 1),
-                        "Gmodmul_per_s_algorithmic": round(alg / s / 1e9, 2),
-                        "Gredc_per_s_executed": round(executed / s / 1e9, 2)}
-    # The paper's three reductions on the same operands: Algorithm 2 (the
-    # product path), Algorithm 3 (Fourier-prime REDC) and Algorithm 1 (Barrett
-    # on ordinary residues).  pow is ALU-bound: 47 reductions per element.
-    alg = {}
+    pw = {"ms": round(s * 1e3, 4), "pow_per_s": round(e.size / s, 1),
+          "Gmodmul_per_s_algorithmic": round(alg / s / 1e9, 2),
+          "Gredc_per_s_executed": round(executed / s / 1e9, 2)}
+    if not reductions:
+        return pw, None
+    red = {}
     for name, fn in (("alg2_montgomery", lambda: mont.pow(prm, dbase, dexp, out=dout)),
                      ("alg3_fourier", lambda: mont.pow_fourier(prm, dbase, dexp, out=dout)),
                      ("alg1_barrett", lambda: mont.pow_barrett(P, dbase, dexp, out=dout))):
         s = timed(torch, fn, 10)
-        alg[name] = {"pow_ms": round(s * 1e3, 4), "Gredc_per_s": round(executed / s / 1e9, 1)}
+        red[name] = {"pow_ms": round(s * 1e3, 4), "Gredc_per_s": round(executed / s / 1e9, 1)}
+    del dbase, dexp, dout
     n = 1 << 28
     xa = torch.randint(0, P, (n,), dtype=torch.int32, device=dev)
     xb = torch.randint(0, P, (n,), dtype=torch.int32, device=dev)
@@ -271,13 +307,9 @@ def extras(torch, mont, wl, dev):
                      ("alg3_fourier", lambda: mont.mul_fourier(prm, xa, xb, out=xo)),
                      ("alg1_barrett", lambda: mont.mul_barrett(P, xa, xb, out=xo))):
         s = timed(torch, fn, 10)
-        alg[name]["mul_n2^28_us"] = round(s * 1e6, 1)
-        alg[name]["mul_GB_per_s"] = round(12 * n / s / 1e9, 1)
-    out["reductions_P998244353"] = alg
-    del dbase, dexp, dout, xa, xb, xo
-    out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
-    out["serving"] = serving_extra(torch, wl, dev)
-    return out
+        red[name]["mul_n2^28_us"] = round(s * 1e6, 1)
+        red[name]["mul_GB_per_s"] = round(12 * n / s / 1e9, 1)
+    return pw, red
 
 
 # Poisson arrival rate of the serving workload, calibrated once to about 70 %

@@ -16,7 +16,8 @@ namespace {
 // T R^-1 = q1 - q2 + q3 (mod P) with the sum in (-(P-1), 2(P-1)).  For P
 // above 2^30 the sum leaves the int32 range, so the sign-mask corrections of
 // the paper are replaced by an explicit borrow: s = q1 + q3 < 2P fits in 32
-// bits, and the result is s - q2 (+P on borrow, -P when >= P).
+// bits; d = s - q2 gets P added back on borrow, which leaves it in [0, 2P),
+// and one conditional subtraction makes it canonical.
 __device__ __forceinline__ uint32_t redc_fourier(uint64_t T, uint32_t P) {
   const uint32_t K = P - 1;
   const uint32_t q1 = (uint32_t)(T >> 32), r1 = (uint32_t)T;
@@ -24,25 +25,28 @@ __device__ __forceinline__ uint32_t redc_fourier(uint64_t T, uint32_t P) {
   const uint32_t q2 = (uint32_t)(u >> 32), r2 = (uint32_t)u;
   const uint32_t q3 = __umulhi(r2, K);
   const uint32_t s = q1 + q3;
-  const uint32_t d = s - q2;
-  const uint32_t neg = d + P;             // q1 + q3 < q2: the sum was negative
+  uint32_t d = s - q2;
+  d = s < q2 ? d + P : d;                 // negative sum: add P back
   const uint32_t dm = d - P;
-  const uint32_t pos = dm < d ? dm : d;   // canonical form of a sum in [0, 2P)
-  return s < q2 ? neg : pos;
+  return dm < d ? dm : d;
 }
 
 // Algorithm 1 (Barrett), on ordinary residues: with k the bit length of P and
 // Pb = floor(2^(2k) / P),  m = floor(ab / 2^k),  q = floor(m Pb / 2^k),
-// t = ab - qP < 4P, then at most three subtractions of P.
-__device__ __forceinline__ uint32_t barrett_mul(uint32_t a, uint32_t b, uint32_t P, uint64_t Pb, uint32_t k) {
+// t = ab - qP in [0, 4P).  For a, b < P every factor fits in 32 bits:
+// m < 2^k <= 2^31, Pb < 2^(k+1) <= 2^32 since P > 2^(k-1), and q <= ab/P < P,
+// so each product is one 32x32->64 multiply.  The correction loop (at most
+// three subtractions of P) is taken as one conditional subtraction of 2P and
+// one of P, which gives the same result for every t < 4P.
+__device__ __forceinline__ uint32_t barrett_mul(uint32_t a, uint32_t b, uint32_t P, uint32_t Pb, uint32_t k) {
   const uint64_t ab = (uint64_t)a * b;
-  const uint64_t m = ab >> k;
-  const uint64_t q = (m * Pb) >> k;
-  uint64_t t = ab - q * P;
-  t = t >= P ? t - P : t;
-  t = t >= P ? t - P : t;
-  t = t >= P ? t - P : t;
-  return (uint32_t)t;
+  const uint32_t m = (uint32_t)(ab >> k);
+  const uint32_t q = (uint32_t)(((uint64_t)m * Pb) >> k);
+  const uint64_t t = ab - (uint64_t)q * P;             // [0, 4P), up to 33 bits
+  const uint64_t d = t - 2 * (uint64_t)P;              // wraps iff t < 2P
+  const uint32_t t1 = (int64_t)d < 0 ? (uint32_t)t : (uint32_t)d;   // [0, 2P)
+  const uint32_t t2 = t1 - P;
+  return t2 < t1 ? t2 : t1;
 }
 
 
@@ -51,7 +55,7 @@ enum AltAlg { ALG_FOURIER = 0, ALG_BARRETT = 1 };
 struct AltMod {
   uint32_t P;
   uint32_t k;     // Barrett: bit length of P
-  uint64_t Pb;    // Barrett: floor(2^(2k) / P)
+  uint32_t Pb;    // Barrett: floor(2^(2k) / P), below 2^32 for odd P
 };
 
 template <int ALG>
@@ -133,7 +137,7 @@ bool barrett_setup(uint32_t P, AltMod& md) {
   while ((1u << k) <= P) k++;        // bit length: 2^(k-1) <= P < 2^k
   md.P = P;
   md.k = k;
-  md.Pb = (((uint64_t)1) << (2 * k)) / P;
+  md.Pb = (uint32_t)((((uint64_t)1) << (2 * k)) / P);
   return true;
 }
 
