@@ -140,6 +140,17 @@ def main():
     out0 = sets[0][4][:4096].cpu().numpy().view(np.uint32)
     assert np.array_equal(out0, oracle.mont_mul(P, a[:4096], b[:4096])), "mont_mul mismatch in bench"
 
+    # Measured HBM comparators on the same resident arrays: torch's int32 add
+    # moves exactly mont_mul's bytes (2 reads + 1 write per element), a copy
+    # moves 8 bytes per element.
+    _, da0, db0, _, do0 = sets[0]
+    ref = {}
+    for name, nbytes, fn in (("torch_add_int32", 12.0 * n, lambda: torch.add(da0, db0, out=do0)),
+                             ("torch_copy_int32", 8.0 * n, lambda: do0.copy_(da0))):
+        s = timed(torch, fn, 10)
+        ref[name] = {"GB_per_s": round(nbytes / s / 1e9, 1), "frac_of_peak": round(nbytes / s / 1e9 / HBM_PEAK_GBS, 4)}
+    log("comparators: %s" % ref)
+
     traffic = None
     if n == MUL_TRAFFIC["n"] and elementwise_src_hash() == MUL_TRAFFIC["src_hash"]:
         traffic = MUL_TRAFFIC["bytes"]
@@ -163,7 +174,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "mont_mul", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": mul_bytes,
-                     "avg_launch_ms": round(mul_avg_s * 1e3, 4)},
+                     "avg_launch_ms": round(mul_avg_s * 1e3, 4),
+                     "measured_comparators": ref,
+                     "frac_of_same_traffic_add": round(achieved / ref["torch_add_int32"]["GB_per_s"], 4)},
     }
 
     if args.copy_calibration:

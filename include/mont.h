@@ -27,6 +27,8 @@
  *     (launch errors) are reported as MONT_EHIP.
  *   - Operands outside [0, P) for mont_mul, mont_muladd and mont_pow give a
  *     deterministic but unspecified value (Algorithm 2 needs a_bar*b_bar < RP).
+ *     The checked mode is mont_check_range below, enqueued on the same
+ *     stream before the call.
  */
 #ifndef MONT_H
 #define MONT_H
@@ -114,6 +116,19 @@ MONT_API mont_status mont_muladd(const mont_params* prm, const uint32_t* d_a, co
  */
 MONT_API mont_status mont_pow(const mont_params* prm, const uint32_t* d_base, const uint32_t* d_exp, uint32_t* d_out,
                      size_t n, void* stream);
+
+/*
+ * mont_check_range -- checked mode of the operand contract above: if any
+ * d_x[i] >= P for i < n, stores MONT_ERANGE into the device word *d_status;
+ * otherwise it does not write *d_status at all.  A status word the caller has
+ * zeroed therefore accumulates over any number of checks (on one stream or
+ * several), and the caller reads it after synchronizing.  P is any nonzero
+ * bound (the modulus for residues and coefficients).  d_status must be a
+ * 4-byte aligned device pointer.  Reads n words from HBM; not needed on the
+ * fast path.  Errors: MONT_EINVAL (P == 0, NULL or misaligned pointer),
+ * MONT_EHIP.
+ */
+MONT_API mont_status mont_check_range(uint32_t P, const uint32_t* d_x, size_t n, int32_t* d_status, void* stream);
 
 /*
  * The paper's other two modular multiplications, for comparison with

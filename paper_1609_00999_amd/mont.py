@@ -27,6 +27,10 @@ class MontParams(ctypes.Structure):
                                                                     self.k)
 
 
+# mont_status values (include/mont.h)
+OK, EINVAL, ERANGE, ENOROOT, ENOMEM, EHIP, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+
+
 class MontError(RuntimeError):
     def __init__(self, status: int, what: str = ""):
         self.status = status
@@ -57,6 +61,7 @@ def lib() -> ctypes.CDLL:
         getattr(L, name).argtypes = [pp, c_vp, c_vp, c_vp, c_size, c_vp]
     for name in ("modmul_barrett", "modpow_barrett"):
         getattr(L, name).argtypes = [c_u32, c_vp, c_vp, c_vp, c_size, c_vp]
+    L.mont_check_range.argtypes = [c_u32, c_vp, c_size, c_vp, c_vp]
     L.mont_batch_reserve.argtypes = [ctypes.c_int, ctypes.POINTER(c_vp)]
     L.mont_batch_update.argtypes = [c_vp, c_vp, ctypes.c_int, c_vp]
     L.mont_batch_mul.argtypes = [c_vp, c_vp]
@@ -142,6 +147,78 @@ def empty_like_u32(t):
     return torch.empty(t.shape, dtype=t.dtype, device=t.device)
 
 
+# --------------------------------------------------------------------------
+# checked mode: operands must lie in [0, P) (Algorithm 2 needs a*b < R P);
+# when on, every call first enqueues mont_check_range on its operands
+# --------------------------------------------------------------------------
+
+_checked_depth = 0
+_status_words = {}
+
+
+def _status_word(device):
+    torch = _torch()
+    key = device.index if device.index is not None else torch.cuda.current_device()
+    w = _status_words.get(key)
+    if w is None:
+        w = _status_words[key] = torch.zeros(1, dtype=torch.int32, device=device)
+    return w
+
+
+def check_range(P: int, x, status=None):
+    """Enqueue the device-side check that every element of x is below P.  An
+    offending element sets the int32 device word ``status`` (default: this
+    device's checked-mode word) to MONT_ERANGE; the word is never cleared here."""
+    if status is None:
+        status = _status_word(x.device)
+    check(lib().mont_check_range(P, dev_ptr(x, "x"), x.numel(), dev_ptr(status, "status"), stream_handle()),
+          "mont_check_range")
+    return status
+
+
+def _maybe_check(P, *xs):
+    if _checked_depth:
+        for x in xs:
+            check_range(P, x)
+
+
+def checked_status(device=None, reset: bool = True) -> int:
+    """Synchronize and return the checked-mode status word of ``device``
+    (0, or MONT_ERANGE if an operand was out of range since the last reset)."""
+    torch = _torch()
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    w = _status_word(dev)
+    v = int(w.item())
+    if reset:
+        w.zero_()
+    return v
+
+
+class checked:
+    """Checked mode for a block: ``with mont.checked(): ...``.  Every
+    elementwise call inside verifies its residue operands on the device; on
+    exit the block synchronizes and raises MontError(MONT_ERANGE) if any
+    operand was outside [0, P).  Blocks nest."""
+
+    def __enter__(self):
+        global _checked_depth
+        if _checked_depth == 0:
+            for w in _status_words.values():
+                w.zero_()
+        _checked_depth += 1
+        return self
+
+    def __exit__(self, et, ev, tb):
+        global _checked_depth
+        _checked_depth -= 1
+        if _checked_depth == 0 and et is None:
+            for key in list(_status_words):
+                st = checked_status("cuda:%d" % key)
+                if st != 0:
+                    raise MontError(st, "checked mode: operand outside [0, P)")
+        return False
+
+
 def _unary(fn, prm, x, out, name):
     if out is None:
         out = empty_like_u32(x)
@@ -169,6 +246,7 @@ def mul(prm: MontParams, a, b, out=None):
         out = empty_like_u32(a)
     if out.numel() != a.numel():
         raise ValueError("out size differs")
+    _maybe_check(prm.P, a, b)
     check(lib().mont_mul(ctypes.byref(prm), dev_ptr(a, "a"), dev_ptr(b, "b"), dev_ptr(out, "out"), a.numel(),
                          stream_handle()), "mont_mul")
     return out
@@ -182,6 +260,7 @@ def muladd(prm: MontParams, a, b, c, out=None):
         out = empty_like_u32(a)
     if out.numel() != a.numel():
         raise ValueError("out size differs")
+    _maybe_check(prm.P, a, b, c)
     check(lib().mont_muladd(ctypes.byref(prm), dev_ptr(a, "a"), dev_ptr(b, "b"), dev_ptr(c, "c"),
                             dev_ptr(out, "out"), a.numel(), stream_handle()), "mont_muladd")
     return out
@@ -195,14 +274,16 @@ def pow(prm: MontParams, base, exp, out=None):  # noqa: A001 - mirrors mont_pow
         out = empty_like_u32(base)
     if out.numel() != base.numel():
         raise ValueError("out size differs")
+    _maybe_check(prm.P, base)
     check(lib().mont_pow(ctypes.byref(prm), dev_ptr(base, "base"), dev_ptr(exp, "exp"), dev_ptr(out, "out"),
                          base.numel(), stream_handle()), "mont_pow")
     return out
 
 
-def _binary(fn, first, a, b, out, name):
+def _binary(fn, first, a, b, out, name, P, check_b):
     if a.numel() != b.numel():
         raise ValueError("operand sizes differ")
+    _maybe_check(P, a, *((b,) if check_b else ()))
     if out is None:
         out = empty_like_u32(a)
     if out.numel() != a.numel():
@@ -213,22 +294,22 @@ def _binary(fn, first, a, b, out, name):
 
 def mul_fourier(prm: MontParams, a, b, out=None):
     """Algorithm 3 (Fourier-prime REDC) elementwise; same result as mul()."""
-    return _binary(lib().mont_mul_fourier, ctypes.byref(prm), a, b, out, "mont_mul_fourier")
+    return _binary(lib().mont_mul_fourier, ctypes.byref(prm), a, b, out, "mont_mul_fourier", prm.P, True)
 
 
 def pow_fourier(prm: MontParams, base, exp, out=None):
     """pow() with Algorithm 3 in place of Algorithm 2; same result."""
-    return _binary(lib().mont_pow_fourier, ctypes.byref(prm), base, exp, out, "mont_pow_fourier")
+    return _binary(lib().mont_pow_fourier, ctypes.byref(prm), base, exp, out, "mont_pow_fourier", prm.P, False)
 
 
 def mul_barrett(P: int, a, b, out=None):
     """Algorithm 1 (Barrett) on ordinary residues: a*b mod P."""
-    return _binary(lib().modmul_barrett, P, a, b, out, "modmul_barrett")
+    return _binary(lib().modmul_barrett, P, a, b, out, "modmul_barrett", P, True)
 
 
 def pow_barrett(P: int, base, exp, out=None):
     """Ordinary a^e mod P with Algorithm 1 products."""
-    return _binary(lib().modpow_barrett, P, base, exp, out, "modpow_barrett")
+    return _binary(lib().modpow_barrett, P, base, exp, out, "modpow_barrett", P, False)
 
 
 class VecDesc(ctypes.Structure):

@@ -155,6 +155,9 @@ def polymul(ctx: Context, prime_id: int, a, b, out=None, scratch=None):
         out = torch.empty(da + db + 1, dtype=a.dtype, device=a.device)
     if out.numel() != da + db + 1:
         raise ValueError("out must hold da+db+1 coefficients")
+    if mont._checked_depth:
+        P = ctx.prime(prime_id)[0].P
+        mont._maybe_check(P, a, b)
     need = scratch_bytes(da, db)
     if need and scratch is None:
         scratch = torch.empty((need + 3) // 4, dtype=torch.int32, device=a.device)

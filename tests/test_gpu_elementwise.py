@@ -237,3 +237,40 @@ def test_alt_reduction_errors(M):
         M.mul_barrett(10, x, x)
     assert np.array_equal(host(M.mul_fourier(prm, x[1:], x[1:])), oracle.mont_mul(2013265921, np.ones(7, np.uint32),
                                                                                  np.ones(7, np.uint32)))
+
+
+def test_checked_mode(M):
+    """mont_check_range flags operands outside [0, P) on the device; the
+    checked() block raises MONT_ERANGE and leaves in-range work untouched."""
+    P = wl.PRIMES_BW[1]
+    prm = M.setup(P)
+    rng = np.random.default_rng(77)
+    for n in (1, 3, 4, 5, 4097, 100003):
+        for off in (0, 1):
+            x = rng.integers(0, P, n + off, dtype=np.uint32)
+            st = torch.zeros(1, dtype=torch.int32, device="cuda")
+            dx = dev(x)[off:]
+            M.check_range(P, dx, st)
+            assert int(st.item()) == 0
+            bad = x.copy()
+            bad[off + (n - 1) // 2] = P               # the first value out of range
+            M.check_range(P, dev(bad)[off:], st)
+            assert int(st.item()) == M.ERANGE
+    a = rng.integers(0, P, 4096, dtype=np.uint32)
+    b = a.copy()
+    b[4095] = 0xFFFFFFFF
+    with M.checked():
+        got = host(M.mul(prm, dev(a), dev(a)))
+    assert np.array_equal(got, oracle.mont_mul(P, a, a))
+    with pytest.raises(M.MontError) as ei:
+        with M.checked():
+            M.mul(prm, dev(a), dev(b))
+    assert ei.value.status == M.ERANGE
+    with pytest.raises(M.MontError):
+        with M.checked():
+            M.pow(prm, dev(b), dev(a))              # the base is checked, the exponent is not
+    with M.checked():
+        M.pow(prm, dev(a), dev(b))
+    assert M.checked_status() == 0
+    with pytest.raises(M.MontError):
+        M.check_range(0, dev(a), torch.zeros(1, dtype=torch.int32, device="cuda"))
