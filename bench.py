@@ -245,7 +245,7 @@ def timed(torch, fn, reps=5):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-EXTRAS = ("pipeline", "pow", "reductions", "polymul", "serving")
+EXTRAS = ("pipeline", "pow", "reductions", "mont64", "polymul", "serving")
 
 
 def extras(torch, mont, wl, dev, which=EXTRAS):
@@ -259,6 +259,8 @@ def extras(torch, mont, wl, dev, which=EXTRAS):
             out["pow_n2^24"] = pw
         if red is not None:
             out["reductions_P998244353"] = red
+    if "mont64" in which:
+        out["mont64"] = mont64_extra(torch, wl, dev)
     if "polymul" in which:
         out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
     if "serving" in which:
@@ -323,6 +325,40 @@ def pow_extras(torch, mont, wl, dev, reductions):
         red[name]["mul_n2^28_us"] = round(s * 1e6, 1)
         red[name]["mul_GB_per_s"] = round(12 * n / s / 1e9, 1)
     return pw, red
+
+
+def mont64_extra(torch, wl, dev):
+    """64-bit residues (R = 2^64): mul and mul-add over 2^27 words per array
+    (1 GiB each, HBM-bound, 24 and 32 bytes per element) for each 63/62-bit
+    prime, and 2^22 powers with 64-bit exponents (ALU-bound, 95 REDC each)."""
+    from paper_1609_00999_amd import mont64
+    n = 1 << 27
+    res = {"n": n, "mul": {}, "muladd": {}}
+    for pi, P in enumerate(wl.PRIMES64):
+        prm = mont64.setup(P)
+        g = torch.Generator(device=dev)
+        g.manual_seed(900 + pi)
+        # residues uniform in [0, P), generated on the device
+        a, b, c = (torch.randint(0, P, (n,), dtype=torch.int64, device=dev, generator=g) for _ in range(3))
+        o = torch.empty_like(a)
+        s = timed(torch, lambda: mont64.mul(prm, a, b, out=o), 10)
+        res["mul"][str(P)] = {"us": round(s * 1e6, 1), "GB_per_s": round(24 * n / s / 1e9, 1),
+                              "frac_of_peak": round(24 * n / s / 1e9 / HBM_PEAK_GBS, 4),
+                              "Gmodmul_per_s": round(n / s / 1e9, 2)}
+        s = timed(torch, lambda: mont64.muladd(prm, a, b, c, out=o), 10)
+        res["muladd"][str(P)] = {"us": round(s * 1e6, 1), "GB_per_s": round(32 * n / s / 1e9, 1),
+                                 "frac_of_peak": round(32 * n / s / 1e9 / HBM_PEAK_GBS, 4)}
+        del a, b, c, o
+    P = wl.PRIMES64[3]
+    prm = mont64.setup(P)
+    base, e = wl.pow64_inputs()
+    dbase = torch.from_numpy(base.view(np.int64)).to(dev)
+    dexp = torch.from_numpy(e.view(np.int64)).to(dev)
+    dout = torch.empty_like(dbase)
+    s = timed(torch, lambda: mont64.pow(prm, dbase, dexp, out=dout), 10)
+    res["pow_n2^22"] = {"P": P, "ms": round(s * 1e3, 4), "pow_per_s": round(base.size / s, 1),
+                        "Gredc_per_s_executed": round(95 * base.size / s / 1e9, 2)}
+    return res
 
 
 # Poisson arrival rate of the serving workload, calibrated once to about 70 %

@@ -23,19 +23,21 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle64.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
 _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc into liboracle.so next to it."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    """Compile oracle.c and oracle64.c with gcc into liboracle.so next to them."""
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-                               "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-shared", "-fPIC",
+                               "-o", tmp, *_SRCS])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -66,6 +68,16 @@ def _load():
     lib.orc_ntt.argtypes = [u32, _u32p, u32, u32]
     lib.orc_polymul_ntt.argtypes = [u32, u32, _u32p, u32, _u32p, u32, _u32p, _u32p]
     lib.orc_polymul_ntt.restype = ctypes.c_int
+    u64 = ctypes.c_uint64
+    lib.orc64_setup.argtypes = [u64, ctypes.c_int, _u64p]
+    lib.orc64_setup.restype = ctypes.c_int
+    lib.orc64_to.argtypes = [u64, ctypes.c_int, _u64p, _u64p, sz]
+    lib.orc64_from.argtypes = [u64, u64, _u64p, _u64p, sz]
+    lib.orc64_mul.argtypes = [u64, u64, _u64p, _u64p, _u64p, sz]
+    lib.orc64_muladd.argtypes = [u64, u64, _u64p, _u64p, _u64p, _u64p, sz]
+    lib.orc64_pow.argtypes = [u64, ctypes.c_int, u64, _u64p, _u64p, _u64p, sz]
+    lib.orc_crt.argtypes = [_u32p, ctypes.c_int, _u32p, sz, _u32p, ctypes.c_int]
+    lib.orc_crt.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -266,3 +278,100 @@ def polymul_many(jobs, threads: int | None = None):
     threads = threads or default_threads()
     with ThreadPoolExecutor(threads) as ex:
         return list(ex.map(lambda j: polymul(*j), jobs))
+
+
+# --------------------------------------------------------------------------
+# 64-bit residues (R = 2^64 by default) and Chinese remaindering
+# --------------------------------------------------------------------------
+
+def _p64(x: np.ndarray):
+    return x.ctypes.data_as(_u64p)
+
+
+def _u64(x) -> np.ndarray:
+    x = np.ascontiguousarray(x)
+    if x.dtype != np.uint64:
+        raise TypeError("oracle arrays must be uint64, got %s" % x.dtype)
+    return x
+
+
+class Params64:
+    """Section 3.1 constants for odd modulus P < 2^63 and R = 2^r (r <= 64)."""
+
+    def __init__(self, P: int, r: int = 64):
+        out = (ctypes.c_uint64 * 5)()
+        if _load().orc64_setup(P, r, out) != 0:
+            raise ValueError("invalid modulus %d for R = 2^%d" % (P, r))
+        self.P, self.r = P, r
+        self.Pprime, self.R1, self.R2, self.Rinv, self.k = (int(v) for v in out)
+
+
+def setup64(P: int, r: int = 64) -> Params64:
+    return Params64(P, r)
+
+
+def to_mont64(P: int, a, r: int = 64, threads: int | None = None) -> np.ndarray:
+    a = _u64(a)
+    out = np.empty_like(a)
+    lib = _load()
+    _run_chunked(lambda s, e: lib.orc64_to(P, r, _p64(a[s:e]), _p64(out[s:e]), e - s), a.size, threads)
+    return out
+
+
+def from_mont64(P: int, x, r: int = 64, threads: int | None = None) -> np.ndarray:
+    x = _u64(x)
+    prm = Params64(P, r)
+    out = np.empty_like(x)
+    lib = _load()
+    _run_chunked(lambda s, e: lib.orc64_from(P, prm.Rinv, _p64(x[s:e]), _p64(out[s:e]), e - s), x.size, threads)
+    return out
+
+
+def mont_mul64(P: int, a, b, r: int = 64, threads: int | None = None) -> np.ndarray:
+    a, b = _u64(a), _u64(b)
+    if a.shape != b.shape:
+        raise ValueError("shape mismatch")
+    prm = Params64(P, r)
+    out = np.empty_like(a)
+    lib = _load()
+    _run_chunked(lambda s, e: lib.orc64_mul(P, prm.Rinv, _p64(a[s:e]), _p64(b[s:e]), _p64(out[s:e]), e - s),
+                 a.size, threads)
+    return out
+
+
+def mont_muladd64(P: int, a, b, c, r: int = 64, threads: int | None = None) -> np.ndarray:
+    a, b, c = _u64(a), _u64(b), _u64(c)
+    if not (a.shape == b.shape == c.shape):
+        raise ValueError("shape mismatch")
+    prm = Params64(P, r)
+    out = np.empty_like(a)
+    lib = _load()
+    _run_chunked(lambda s, e: lib.orc64_muladd(P, prm.Rinv, _p64(a[s:e]), _p64(b[s:e]), _p64(c[s:e]),
+                                               _p64(out[s:e]), e - s), a.size, threads)
+    return out
+
+
+def mont_pow64(P: int, base, exp, r: int = 64, threads: int | None = None) -> np.ndarray:
+    base, exp = _u64(base), _u64(exp)
+    if base.shape != exp.shape:
+        raise ValueError("shape mismatch")
+    prm = Params64(P, r)
+    out = np.empty_like(base)
+    lib = _load()
+    _run_chunked(lambda s, e: lib.orc64_pow(P, r, prm.Rinv, _p64(base[s:e]), _p64(exp[s:e]), _p64(out[s:e]),
+                                            e - s), base.size, threads)
+    return out
+
+
+def crt(primes, residues, limbs: int) -> np.ndarray:
+    """Integers X in [0, prod(primes)) with X = residues[j] mod primes[j], as
+    ``limbs`` little-endian uint32 words per element (shape (n, limbs))."""
+    pr = np.ascontiguousarray(np.asarray(primes, dtype=np.uint32))
+    res = _u32(np.ascontiguousarray(np.asarray(residues, dtype=np.uint32)))
+    if res.ndim != 2 or res.shape[0] != pr.size:
+        raise ValueError("residues must have shape (len(primes), n)")
+    n = res.shape[1]
+    out = np.empty((n, limbs), dtype=np.uint32)
+    if _load().orc_crt(_p(pr), pr.size, _p(res), n, _p(out), limbs) != 0:
+        raise ValueError("bad moduli or too few limbs")
+    return out

@@ -21,11 +21,18 @@ P_POW = 998244353               # 119 * 2^23 + 1
 PRIMES_NTT = (2013265921, 1811939329, 2113929217, 1711276033,
               1107296257, 2130706433, 1224736769, 2088763393)
 
+# 62- and 63-bit primes for the 64-bit residues: 29*2^57+1, 87*2^56+1,
+# 505*2^54+1 and 2^63-25 (the largest prime below 2^63).
+PRIMES64 = (4179340454199820289, 6269010681299730433, 9097271247288401921, 9223372036854775783)
+
 SEED_PLAIN = 1
 SEED_BW_BASE = 200
 SEED_POW = 3
 SEED_BATCH = 4
 SEED_SERVE = 5
+SEED_BW64_BASE = 600
+SEED_POW64 = 7
+SEED_CRT = 8
 
 
 def uniform(rng: np.random.Generator, lo: int, hi: int, n: int) -> np.ndarray:
@@ -162,3 +169,23 @@ def request_operands(req: Request, primes=PRIMES_NTT):
     if req.kind == "mul":
         return P, uniform(rng, 0, P, req.size), uniform(rng, 0, P, req.size)
     return P, uniform(rng, 0, P, req.size + 1), uniform(rng, 0, P, req.size + 1)
+
+
+def uniform64(rng: np.random.Generator, lo: int, hi: int, n: int) -> np.ndarray:
+    return rng.integers(lo, hi, size=n, dtype=np.uint64)
+
+
+def bandwidth_triple64(prime_index: int, n: int = 1 << 27):
+    """a, b, c uniform in [0, P) for the 64-bit residue workload (2^27 words
+    of 8 bytes = 1 GiB per array, the same bytes as 2^28 32-bit residues)."""
+    P = PRIMES64[prime_index]
+    rng = np.random.default_rng(SEED_BW64_BASE + prime_index)
+    return P, uniform64(rng, 0, P, n), uniform64(rng, 0, P, n), uniform64(rng, 0, P, n)
+
+
+def pow64_inputs(n: int = 1 << 22, P: int = PRIMES64[3], seed: int = SEED_POW64):
+    """Bases uniform in [1, P), exponents uniform over all 64-bit words."""
+    rng = np.random.default_rng(seed)
+    base = uniform64(rng, 1, P, n)
+    e = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
+    return base, e
