@@ -245,7 +245,7 @@ def timed(torch, fn, reps=5):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-EXTRAS = ("pipeline", "pow", "reductions", "mont64", "polymul", "serving")
+EXTRAS = ("pipeline", "pow", "reductions", "mont64", "crt", "polymul", "serving")
 
 
 def extras(torch, mont, wl, dev, which=EXTRAS):
@@ -261,6 +261,8 @@ def extras(torch, mont, wl, dev, which=EXTRAS):
             out["reductions_P998244353"] = red
     if "mont64" in which:
         out["mont64"] = mont64_extra(torch, wl, dev)
+    if "crt" in which:
+        out["crt_int_products_256"] = crt_extra(torch, wl, dev)
     if "polymul" in which:
         out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
     if "serving" in which:
@@ -358,6 +360,40 @@ def mont64_extra(torch, wl, dev):
     s = timed(torch, lambda: mont64.pow(prm, dbase, dexp, out=dout), 10)
     res["pow_n2^22"] = {"P": P, "ms": round(s * 1e3, 4), "pow_per_s": round(base.size / s, 1),
                         "Gredc_per_s_executed": round(95 * base.size / s / 1e9, 2)}
+    return res
+
+
+def crt_extra(torch, wl, dev):
+    """Exact integer products: 256 pairs of degree d = floor(2^U), U ~ U[8, 18),
+    uint32 coefficients, through three 31-bit primes (768 modular products in
+    one persistent launch) and Garner's reconstruction."""
+    from paper_1609_00999_amd import crt, ntt
+    import oracle
+    batch = wl.int_products()
+    ctx = ntt.Context(wl.PRIMES_NTT, 23)
+    prm = crt.setup(wl.PRIMES_NTT[:3])
+    cb = crt.Batch.from_batch(ctx, prm, batch)
+    work = cb.buffers(dev)
+    coeffs = torch.from_numpy(batch.coeffs.view(np.int32)).to(dev)
+    out = torch.empty((batch.out_len, 3), dtype=torch.int32, device=dev)
+    s = timed(torch, lambda: cb.run(coeffs, out, work), 5)
+    # spot check: the shortest and the longest product against the oracle
+    got = out.cpu().numpy().view(np.uint32)
+    bad = 0
+    for i in (int(np.argmin(batch.da)), int(np.argmax(batch.da))):
+        _, a, b = batch.operands(i)
+        res = [oracle.polymul(P, a % np.uint32(P), b % np.uint32(P)) for P in prm.primes]
+        want = oracle.crt(prm.primes, np.stack(res), 3)
+        c0 = int(batch.c_off[i])
+        bad += int(not np.array_equal(got[c0: c0 + want.shape[0]], want))
+    N = [1 << int(int(a + b + 1 - 1).bit_length()) for a, b in zip(batch.da, batch.db)]
+    redc = 3 * sum(1.5 * n * (n.bit_length() - 1) + n + int(db) + 1 for n, db in zip(N, batch.db))
+    res = {"products": batch.count, "modular_products": 3 * batch.count, "ms": round(s * 1e3, 3),
+           "int_products_per_s": round(batch.count / s, 1), "Gredc_per_s_ntt": round(redc / s / 1e9, 1),
+           "coeff_out_per_s_G": round(batch.out_len / s / 1e9, 3), "spot_check_failures": bad,
+           "tasks": cb.plan.ntasks}
+    cb.close()
+    ctx.close()
     return res
 
 

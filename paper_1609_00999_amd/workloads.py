@@ -189,3 +189,12 @@ def pow64_inputs(n: int = 1 << 22, P: int = PRIMES64[3], seed: int = SEED_POW64)
     base = uniform64(rng, 1, P, n)
     e = rng.integers(0, 1 << 64, size=n, dtype=np.uint64)
     return base, e
+
+
+def int_products(count: int = 256, lo_log2: float = 8, hi_log2: float = 18, seed: int = SEED_CRT) -> PolymulBatch:
+    """count products of two degree-d integer polynomials, d = floor(2^U),
+    U ~ U[lo, hi), coefficients uniform over all uint32 words (the packing
+    of pack_products with the single bound 2^32 in place of a prime)."""
+    rng = np.random.default_rng(seed)
+    d = log_uniform(rng, lo_log2, hi_log2, count)
+    return pack_products((1 << 32,), np.zeros(count, dtype=np.int64), d, d, rng)
