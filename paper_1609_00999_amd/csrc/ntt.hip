@@ -80,7 +80,10 @@ __device__ __forceinline__ Mod mod_of(const PrimeDev& pr) { return Mod{pr.P, pr.
 // apart, or groups of 8 or 16 lanes 64+ words apart) over the banks: the
 // worst wave access is 2-way instead of 16-way, the mean 1.2-way.
 constexpr bool kSwizzle = true;
-__device__ __forceinline__ uint32_t lds_at(uint32_t i) {
+// The key 9 k = (k << 3) | k of row bits k = (i >> 6) & 7 is linear over
+// GF(2) in i, so lds_at(x ^ y) = lds_at(x) ^ lds_at(y): the address of a
+// group element yb | s (s in bits that are zero in yb) is lds_at(yb) ^ lds_at(s).
+__host__ __device__ constexpr uint32_t lds_at(uint32_t i) {
   if constexpr (kSwizzle) {
     const uint32_t k = (i >> 6) & 7u;
     return i ^ ((k << 3) | k);
@@ -133,10 +136,10 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
         w[(1 << t) - 1 + jj] = ldg(tw, (1u << (s_lo + t + rs)) + t0 + ((uint32_t)jj << (s_lo + rs)));
 #pragma nounroll
     for (int a = 0; a < NA; a++) {
-      const uint32_t yb = (uint32_t)(a * off) + base;
+      const uint32_t pb = lds_at((uint32_t)(a * off) + base);
       uint32_t v[E];
 #pragma unroll
-      for (int j = 0; j < E; j++) v[j] = X[lds_at(yb + ((uint32_t)j << a_lo))];
+      for (int j = 0; j < E; j++) v[j] = X[pb ^ lds_at((uint32_t)j << a_lo)];
       if constexpr (!INV) {
 #pragma unroll
         for (int t = R - 1; t >= 0; t--) {
@@ -165,7 +168,7 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
         }
       }
 #pragma unroll
-      for (int j = 0; j < E; j++) X[lds_at(yb + ((uint32_t)j << a_lo))] = v[j];
+      for (int j = 0; j < E; j++) X[pb ^ lds_at((uint32_t)j << a_lo)] = v[j];
     }
   }
   __syncthreads();
@@ -227,7 +230,8 @@ __device__ __forceinline__ void lds_dit(uint32_t* X, int lr, int lc, int rs, uin
 //     reaches, so lds_at(yb + j 2^s) = lds_at(yb) + j 2^s;
 //   * the group lies inside one 64-word row (first stage + R <= 6): the row
 //     key is shared, so lds_at(yb + j 2^s) = lds_at(yb) ^ (j 2^s);
-//   * otherwise the general lds_at.
+//   * otherwise, by the linearity of the key, lds_at(yb) ^ lds_at(j 2^s) with
+//     the second term a compile-time constant.
 // The inverse uses the forward's round sizes in reverse order, so its first
 // rounds also fall in the cheap cases.
 // ---------------------------------------------------------------------------
@@ -264,7 +268,10 @@ __device__ __forceinline__ uint32_t group_addr(uint32_t yb, uint32_t pb) {
   constexpr uint32_t step = (uint32_t)J << A_LO;
   if constexpr (A_LO >= 9) return pb + step;
   else if constexpr (A_LO + R <= 6) return pb ^ step;
-  else return lds_at(yb + step);
+  else {
+    constexpr uint32_t cs = lds_at(step);
+    return pb ^ cs;
+  }
 }
 
 template <int A_LO, int R, int J>
