@@ -105,7 +105,14 @@ typedef struct ntt_plan ntt_plan;
  * each with its own prime, for ONE persistent launch.  Products with N <=
  * 2^13 are single tasks; longer ones are split into column tiles of both
  * operands, row blocks (forward rows, pointwise product, inverse rows) and
- * inverse column tiles, with per-product completion counters.  Tasks are
+ * inverse column tiles, with per-product completion counters.  A longer
+ * product whose length L = da+db+1 lies just above h = N/2 (both operands
+ * shorter than h, and the top m = L - h coefficients of each operand having
+ * a product of length <= N/4) is computed as the cyclic product of length h
+ * plus the product of those top coefficients, and a fix-up pass after the
+ * launch subtracts the wrapped part and stores the top coefficients; this
+ * cuts about a quarter of such a product's butterflies.  The result is the
+ * same.  Tasks are
  * ordered so that every prerequisite precedes its dependants: forward column
  * tiles, half the single tasks, row blocks, the other half, inverse column
  * tiles, each group longest-first, or shuffled within groups when
@@ -121,7 +128,7 @@ MONT_API mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* des
  * max_tasks tasks (device arrays plus pinned host staging), for callers that
  * plan a new batch often (a serving loop).  It holds no batch until
  * ntt_plan_update.  ntt_plan_task_count(da, db) gives the tasks one product
- * adds.  Errors: MONT_EINVAL, MONT_ENOMEM.
+ * adds (both parts of a split product).  Errors: MONT_EINVAL, MONT_ENOMEM.
  */
 MONT_API mont_status ntt_plan_reserve(const ntt_ctx* ctx, int max_products, uint32_t max_tasks, ntt_plan** out);
 MONT_API uint32_t ntt_plan_task_count(uint32_t da, uint32_t db);
@@ -147,13 +154,14 @@ MONT_API mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, 
 /*
  * ntt_plan_execute -- zeroes the scratch header with a fill kernel, then runs
  * the whole batch in one persistent launch of `grid` workgroups (0 = the
- * default) that take tasks from a device counter.  Waits on another task's
- * completion spin at most spin_limit sleeps (0 = 2^24); on expiry the launch
- * records a timeout, skips the dependent tasks and drains.  d_scratch must
+ * default) that take tasks from a device counter, then (if the plan split a
+ * product) one fix-up kernel.  Waits on another task's completion spin at
+ * most spin_limit sleeps (0 = 2^24); on expiry the launch records a timeout,
+ * skips the dependent tasks and drains.  d_scratch must
  * hold the plan's scratch bytes; d_in and d_out the plan's word counts.  The
- * result is identical for every grid size and task order.  Enqueues two
- * kernels and no memset or allocation, so the call may be captured in a HIP
- * graph.  d_scratch must be 16-byte aligned (MONT_EINVAL otherwise).  Calls
+ * result is identical for every grid size and task order.  Enqueues two or
+ * three kernels and no memset or allocation, so the call may be captured in a
+ * HIP graph.  d_scratch must be 16-byte aligned (MONT_EINVAL otherwise).  Calls
  * that share a scratch buffer must not overlap.
  */
 MONT_API mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_in, uint32_t* d_out, void* d_scratch,

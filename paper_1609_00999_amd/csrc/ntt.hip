@@ -53,15 +53,33 @@ struct PrimeDev {
   uint32_t s2[32];          // s2[n] = R^2 N^-1 mod P (REDC(x s2) = x R / N)
 };
 
-// One product in a batch plan.
+// One product in a batch plan.  Its transform length 2^n is normally the
+// least power of two >= da + db + 1; a plan may also force a shorter length,
+// and then the product is the cyclic convolution of that length (the
+// coefficients of a b reduced modulo x^(2^n) - 1).  It stores nout =
+// min(da + db + 1, 2^n) coefficients at c_off in the output buffer, or in the
+// plan's scratch when to_scr is set.
 struct ProdDev {
   uint32_t prime_id, n, da, db;
   uint64_t a_off, b_off, c_off, scr_off;
   uint32_t lc;              // log2 of the columns per column tile
   uint32_t ntiles;          // column tiles per operand
   uint32_t nblocks;         // row blocks (2^(n - 13))
-  uint32_t pad;
+  uint32_t nout;            // coefficients stored
+  uint32_t to_scr;          // 1: c_off is an offset into the scratch buffer
+  uint32_t pad[3];
 };
+
+// Fix-up of a product split into its cyclic part and its top part: with
+// h = 2^(n-1) and m = da + db + 1 - h, c[k] -= t[m-1+k] and c[h+k] = t[m-1+k]
+// for k < m, where t is the product of the top m coefficients of a and b.
+struct FixDev {
+  uint64_t c_off;           // product output, in the output buffer
+  uint64_t t_off;           // top product, in the scratch buffer
+  uint32_t m, h, P;
+  uint32_t chunk0;          // first of its ceil(m / kFixChunk) chunks in the fix-up launch
+};
+constexpr uint32_t kFixChunk = 1024;
 
 enum TaskKind : uint32_t { T_SMALL = 0, T_COLF_A = 1, T_COLF_B = 2, T_ROW = 3, T_COLI = 4 };
 
@@ -416,7 +434,7 @@ __device__ __forceinline__ void st_out(uint32_t* p, uint32_t v) {
 // leaves a b / N), inverse transform, store of the da + db + 1 coefficients.
 template <int NT, int RM>
 __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const uint32_t* a, uint32_t da, const uint32_t* b,
-                                uint32_t db, uint32_t* out, uint32_t* X) {
+                                uint32_t db, uint32_t* out, uint32_t nout, uint32_t* X) {
   const Mod md = mod_of(pr);
   const uint32_t N = 1u << n;
   const uint32_t sc = pr.s2[n];
@@ -429,7 +447,6 @@ __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const
   for (uint32_t e = threadIdx.x; e < N; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(N + e)], md);
   __syncthreads();
   if (n > 0) lds_dit<NT, RM>(X, n, 0, 0, 0, pr.twi, md);
-  const uint32_t nout = da + db + 1;
   for (uint32_t e = threadIdx.x; e < nout; e += NT) out[e] = X[lds_at(e)];
   __syncthreads();
 }
@@ -614,7 +631,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_direct(Di
   const uint32_t N = 1u << g.n;
   const uint32_t S = 1u << kRowLog;
   switch (g.kind) {
-    case D_SMALL_POLY: exec_small_poly<NT, RM>(pr, g.n, g.a, g.da, g.b, g.db, g.out, X); break;
+    case D_SMALL_POLY: exec_small_poly<NT, RM>(pr, g.n, g.a, g.da, g.b, g.db, g.out, g.da + g.db + 1, X); break;
     case D_COLF:
       if (bid < g.ntiles) exec_col_dif<NT, RM, false>(pr, g.n, g.lc, bid, g.a, g.da, 0u, g.scr, X);
       else exec_col_dif<NT, RM, false>(pr, g.n, g.lc, bid - g.ntiles, g.b, g.db, pr.s2[g.n], g.scr + N, X);
@@ -702,14 +719,17 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
     if (s_go) {
       switch (kind) {
         case T_SMALL:
-          exec_small_poly<NT, RM>(pr, pd.n, g.in + pd.a_off, pd.da, g.in + pd.b_off, pd.db, g.out + pd.c_off, X);
+          exec_small_poly<NT, RM>(pr, pd.n, g.in + pd.a_off, pd.da, g.in + pd.b_off, pd.db,
+                                  (pd.to_scr ? g.scr : g.out) + pd.c_off, pd.nout, X);
           break;
         case T_COLF_A: exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X); break;
         case T_COLF_B:
           exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X);
           break;
         case T_ROW: exec_row<NT, RM, true>(pr, kRowLog, ROW_POLY, scr + idx * S, scr + N + idx * S, 0u, X); break;
-        default: exec_col_dit<NT, RM>(pr, pd.n, pd.lc, idx, scr, g.out + pd.c_off, pd.da + pd.db + 1, X); break;
+        default:
+          exec_col_dit<NT, RM>(pr, pd.n, pd.lc, idx, scr, (pd.to_scr ? g.scr : g.out) + pd.c_off, pd.nout, X);
+          break;
       }
       if (kind != T_SMALL && kind != T_COLI) {
         // Publish: every wave waits until its coherent stores have completed,
@@ -723,6 +743,33 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
       }
     }
     __syncthreads();
+  }
+}
+
+// Fix-ups of split products, after the persistent launch, in chunks of
+// kFixChunk coefficients so that a long product's fix-up is spread over the
+// device (a workgroup takes chunks; the fix-up of a chunk is found by binary
+// search on the chunks' first indices).  The cyclic part left c[k] = c_k +
+// c_(h+k); the top product t gives c_(h+k) = t[m-1+k].
+__global__ __launch_bounds__(256) void k_split_fix(const FixDev* fx, uint32_t nfix, uint32_t nchunks, uint32_t* out,
+                                                   const uint32_t* scr) {
+  for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    uint32_t lo = 0, hi = nfix;                  // fx[lo].chunk0 <= c < fx[hi].chunk0
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (fx[mid].chunk0 <= c) lo = mid;
+      else hi = mid;
+    }
+    const FixDev d = fx[lo];
+    uint32_t* cc = out + d.c_off;
+    const uint32_t* t = scr + d.t_off + (d.m - 1);
+    const uint32_t k0 = (c - d.chunk0) * kFixChunk;
+    const uint32_t k1 = min(d.m, k0 + kFixChunk);
+    for (uint32_t k = k0 + threadIdx.x; k < k1; k += 256) {
+      const uint32_t hv = t[k];
+      cc[k] = msub(cc[k], hv, d.P);
+      cc[d.h + k] = hv;
+    }
   }
 }
 
@@ -848,14 +895,18 @@ struct ntt_plan {
   uint64_t in_words = 0, out_words = 0;
   ProdDev* d_prods = nullptr;
   uint2* d_tasks = nullptr;
+  uint32_t nfix = 0;        // split products (count above counts their two parts)
+  uint32_t nchunks = 0;     // fix-up chunks
+  FixDev* d_fix = nullptr;
   int default_grid = 0;
   // Reusable plans (ntt_plan_reserve): device capacity and pinned staging
   // for asynchronous updates; `staged` marks the last upload from staging.
   bool reusable = false;
-  int cap_prods = 0;
+  int cap_prods = 0;        // caller's products; internal capacity is twice that
   uint32_t cap_tasks = 0;
   ProdDev* h_prods = nullptr;
   uint2* h_tasks = nullptr;
+  FixDev* h_fix = nullptr;
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
 };
@@ -1157,19 +1208,47 @@ extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint3
 
 namespace {
 
-// Host side of planning: per-product descriptors, the ordered task list and
-// the scratch layout (header, two counters per product, then 2N words per
-// multi-pass product).
+// Splitting a product whose length L = da + db + 1 is just above h = N/2.
+// With both operands shorter than h, the cyclic product of length h gives
+// c_k + c_(h+k), and the top m = L - h coefficients of a and b (a[h-db ..
+// da], b[h-da .. db]) have a product whose coefficients m-1 .. 2m-2 are
+// c_h .. c_(L-1).  The split is taken when the top product's length 2^nt
+// (>= 2m - 1) is at most N/4: the pair then costs at most 3/4 of the
+// butterflies of the length-N product.  (With 2^nt = N/2 it would save only
+// one stage in log2 N, not worth a second product and the fix-up.)  Only
+// multi-pass products are split: a product of length <= 2^13 is one task
+// whose cost is mostly its fixed overhead.
+bool split_rule(uint32_t da, uint32_t db, int n, uint32_t& m, int& nt) {
+  if (n <= kRowLog) return false;
+  const uint64_t h = 1ull << (n - 1);
+  if ((uint64_t)da + 1 > h || (uint64_t)db + 1 > h) return false;
+  m = (uint32_t)((uint64_t)da + db + 1 - h);
+  nt = ceil_log2(2ull * m - 1);
+  return nt <= n - 2;
+}
+
+uint32_t product_tasks(int n) {
+  if (n <= kRowLog) return 1;
+  const uint32_t ntiles = 1u << (kRowLog - col_lc(n));
+  return 3 * ntiles + (1u << (n - kRowLog));
+}
+
+// Host side of planning: internal products (a product the split rule takes
+// becomes its cyclic part and its top part), the ordered task list, the
+// fix-up list and the scratch layout: header, two counters per internal
+// product, then 2N words per multi-pass product and the top parts' outputs.
 mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
-                       std::vector<ProdDev>& prods, std::vector<uint2>& tasks, uint64_t& scr_words,
-                       uint64_t& in_words, uint64_t& out_words) {
-  prods.assign(count, ProdDev{});
+                       std::vector<ProdDev>& prods, std::vector<uint2>& tasks, std::vector<FixDev>& fixes,
+                       uint32_t& nchunks, uint64_t& scr_words, uint64_t& in_words, uint64_t& out_words) {
+  nchunks = 0;
+  prods.clear();
+  prods.reserve(2 * (size_t)count);
+  fixes.clear();
   tasks.clear();
   std::vector<uint2> colf, small, row, coli;
-  uint64_t scr = kHdrWords + 2ull * count;
-  scr = (scr + 63) & ~63ull;
   in_words = 0;
   out_words = 0;
+  std::vector<uint32_t> top_words;                 // per fix-up: words of its top output
   for (int p = 0; p < count; p++) {
     const polymul_desc& d = descs[p];
     if (d.prime_id >= ctx->params.size() || d.reserved != 0) return MONT_EINVAL;
@@ -1177,30 +1256,72 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
     if (nout > ((uint64_t)1 << 31)) return MONT_ERANGE;
     int n = ceil_log2(nout);
     if ((uint32_t)n > ctx->logmax[d.prime_id]) return MONT_ENOROOT;
-    ProdDev& pd = prods[p];
+    in_words = std::max<uint64_t>(in_words, std::max(d.a_off + d.da + 1, d.b_off + d.db + 1));
+    out_words = std::max<uint64_t>(out_words, d.c_off + nout);
+    ProdDev pd;
     std::memset(&pd, 0, sizeof(pd));
     pd.prime_id = d.prime_id;
-    pd.n = (uint32_t)n;
     pd.da = d.da;
     pd.db = d.db;
     pd.a_off = d.a_off;
     pd.b_off = d.b_off;
     pd.c_off = d.c_off;
-    in_words = std::max<uint64_t>(in_words, std::max(d.a_off + d.da + 1, d.b_off + d.db + 1));
-    out_words = std::max<uint64_t>(out_words, d.c_off + nout);
-    if (n <= kRowLog) {
-      small.push_back(make_uint2((uint32_t)p, T_SMALL << 28));
+    uint32_t m = 0;
+    int nt = 0;
+    if (split_rule(d.da, d.db, n, m, nt)) {
+      const uint32_t h = 1u << (n - 1);
+      pd.n = (uint32_t)(n - 1);                    // cyclic part, straight into the output
+      pd.nout = h;
+      prods.push_back(pd);
+      ProdDev tp = pd;                             // top part, into scratch
+      tp.n = (uint32_t)nt;
+      tp.da = m - 1;
+      tp.db = m - 1;
+      tp.a_off = d.a_off + (h - d.db);
+      tp.b_off = d.b_off + (h - d.da);
+      tp.nout = 2 * m - 1;
+      tp.to_scr = 1;
+      prods.push_back(tp);
+      FixDev f;
+      f.c_off = d.c_off;
+      f.t_off = 0;                                 // set with the scratch layout
+      f.m = m;
+      f.h = h;
+      f.P = ctx->params[d.prime_id].P;
+      f.chunk0 = nchunks;
+      nchunks += (m + kFixChunk - 1) / kFixChunk;
+      fixes.push_back(f);
+      top_words.push_back(2 * m - 1);
     } else {
-      pd.lc = (uint32_t)col_lc(n);
-      pd.ntiles = 1u << (kRowLog - pd.lc);
-      pd.nblocks = 1u << (n - kRowLog);
-      pd.scr_off = scr;
-      scr += 2ull << n;
+      pd.n = (uint32_t)n;
+      pd.nout = (uint32_t)nout;
+      prods.push_back(pd);
     }
   }
+  const int np = (int)prods.size();
+  uint64_t scr = kHdrWords + 2ull * np;
+  scr = (scr + 63) & ~63ull;
+  for (int p = 0, f = 0; p < np; p++) {
+    ProdDev& pd = prods[p];
+    if (pd.n > (uint32_t)kRowLog) {
+      pd.lc = (uint32_t)col_lc((int)pd.n);
+      pd.ntiles = 1u << (kRowLog - pd.lc);
+      pd.nblocks = 1u << (pd.n - kRowLog);
+      pd.scr_off = scr;
+      scr += 2ull << pd.n;
+    }
+    if (pd.to_scr) {
+      pd.c_off = scr;
+      fixes[f].t_off = scr;
+      scr += (top_words[f] + 3) & ~3u;
+      f++;
+    }
+  }
+  for (int p = 0; p < np; p++)
+    if (prods[p].n <= (uint32_t)kRowLog) small.push_back(make_uint2((uint32_t)p, T_SMALL << 28));
   // Cost order: longest products first within each group.
   std::vector<int> big;
-  for (int p = 0; p < count; p++)
+  for (int p = 0; p < np; p++)
     if (prods[p].n > (uint32_t)kRowLog) big.push_back(p);
   std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return prods[x].n > prods[y].n; });
   std::stable_sort(small.begin(), small.end(), [&](uint2 x, uint2 y) { return prods[x.x].n > prods[y.x].n; });
@@ -1233,8 +1354,10 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
 void free_plan(ntt_plan* plan) {
   (void)hipFree(plan->d_prods);
   (void)hipFree(plan->d_tasks);
+  (void)hipFree(plan->d_fix);
   if (plan->h_prods) (void)hipHostFree(plan->h_prods);
   if (plan->h_tasks) (void)hipHostFree(plan->h_tasks);
+  if (plan->h_fix) (void)hipHostFree(plan->h_fix);
   if (plan->staged) (void)hipEventDestroy(plan->staged);
   delete plan;
 }
@@ -1247,25 +1370,32 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
   *out = nullptr;
   std::vector<ProdDev> prods;
   std::vector<uint2> tasks;
+  std::vector<FixDev> fixes;
   uint64_t scr = 0, in_words = 0, out_words = 0;
-  mont_status st = build_plan(ctx, descs, count, order_seed, prods, tasks, scr, in_words, out_words);
+  uint32_t nchunks = 0;
+  mont_status st = build_plan(ctx, descs, count, order_seed, prods, tasks, fixes, nchunks, scr, in_words, out_words);
   if (st != MONT_OK) return st;
   ntt_plan* plan = new (std::nothrow) ntt_plan;
   if (!plan) return MONT_ENOMEM;
   plan->ctx = ctx;
-  plan->count = count;
+  plan->count = (int)prods.size();
   plan->ntasks = (uint32_t)tasks.size();
+  plan->nfix = (uint32_t)fixes.size();
+  plan->nchunks = nchunks;
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
-  if (count > 0) {
-    if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * count) != hipSuccess ||
-        hipMalloc(&plan->d_tasks, sizeof(uint2) * std::max<size_t>(1, tasks.size())) != hipSuccess) {
+  if (!prods.empty()) {
+    if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * prods.size()) != hipSuccess ||
+        hipMalloc(&plan->d_tasks, sizeof(uint2) * std::max<size_t>(1, tasks.size())) != hipSuccess ||
+        (!fixes.empty() && hipMalloc(&plan->d_fix, sizeof(FixDev) * fixes.size()) != hipSuccess)) {
       free_plan(plan);
       return MONT_ENOMEM;
     }
-    if (hipMemcpy(plan->d_prods, prods.data(), sizeof(ProdDev) * count, hipMemcpyHostToDevice) != hipSuccess ||
+    if (hipMemcpy(plan->d_prods, prods.data(), sizeof(ProdDev) * prods.size(), hipMemcpyHostToDevice) != hipSuccess ||
         (tasks.size() && hipMemcpy(plan->d_tasks, tasks.data(), sizeof(uint2) * tasks.size(),
+                                   hipMemcpyHostToDevice) != hipSuccess) ||
+        (fixes.size() && hipMemcpy(plan->d_fix, fixes.data(), sizeof(FixDev) * fixes.size(),
                                    hipMemcpyHostToDevice) != hipSuccess)) {
       free_plan(plan);
       return MONT_EHIP;
@@ -1285,10 +1415,13 @@ extern "C" mont_status ntt_plan_reserve(const ntt_ctx* ctx, int max_products, ui
   plan->reusable = true;
   plan->cap_prods = max_products;
   plan->cap_tasks = max_tasks;
-  if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * max_products) != hipSuccess ||
+  const size_t nint = 2 * (size_t)max_products;    // a split product has two parts
+  if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * nint) != hipSuccess ||
       hipMalloc(&plan->d_tasks, sizeof(uint2) * max_tasks) != hipSuccess ||
-      hipHostMalloc((void**)&plan->h_prods, sizeof(ProdDev) * max_products, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&plan->d_fix, sizeof(FixDev) * max_products) != hipSuccess ||
+      hipHostMalloc((void**)&plan->h_prods, sizeof(ProdDev) * nint, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&plan->h_tasks, sizeof(uint2) * max_tasks, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&plan->h_fix, sizeof(FixDev) * max_products, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming) != hipSuccess) {
     free_plan(plan);
     return MONT_ENOMEM;
@@ -1304,27 +1437,35 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   if (count > plan->cap_prods) return MONT_ERANGE;
   std::vector<ProdDev> prods;
   std::vector<uint2> tasks;
+  std::vector<FixDev> fixes;
   uint64_t scr = 0, in_words = 0, out_words = 0;
-  mont_status st = build_plan(plan->ctx, descs, count, order_seed, prods, tasks, scr, in_words, out_words);
+  uint32_t nchunks = 0;
+  mont_status st = build_plan(plan->ctx, descs, count, order_seed, prods, tasks, fixes, nchunks, scr, in_words,
+                              out_words);
   if (st != MONT_OK) return st;
   if (tasks.size() > plan->cap_tasks) return MONT_ERANGE;
   // The previous upload must have finished reading the staging buffers.
   if (plan->staged_pending && hipEventSynchronize(plan->staged) != hipSuccess) return MONT_EHIP;
   plan->staged_pending = false;
   hipStream_t s = as_stream(stream);
-  if (count > 0) {
-    std::memcpy(plan->h_prods, prods.data(), sizeof(ProdDev) * count);
+  if (!prods.empty()) {
+    std::memcpy(plan->h_prods, prods.data(), sizeof(ProdDev) * prods.size());
     if (!tasks.empty()) std::memcpy(plan->h_tasks, tasks.data(), sizeof(uint2) * tasks.size());
-    if (hipMemcpyAsync(plan->d_prods, plan->h_prods, sizeof(ProdDev) * count, hipMemcpyHostToDevice, s) !=
+    if (!fixes.empty()) std::memcpy(plan->h_fix, fixes.data(), sizeof(FixDev) * fixes.size());
+    if (hipMemcpyAsync(plan->d_prods, plan->h_prods, sizeof(ProdDev) * prods.size(), hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         (!tasks.empty() && hipMemcpyAsync(plan->d_tasks, plan->h_tasks, sizeof(uint2) * tasks.size(),
+                                          hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (!fixes.empty() && hipMemcpyAsync(plan->d_fix, plan->h_fix, sizeof(FixDev) * fixes.size(),
                                           hipMemcpyHostToDevice, s) != hipSuccess) ||
         hipEventRecord(plan->staged, s) != hipSuccess)
       return MONT_EHIP;
     plan->staged_pending = true;
   }
-  plan->count = count;
+  plan->count = (int)prods.size();
   plan->ntasks = (uint32_t)tasks.size();
+  plan->nfix = (uint32_t)fixes.size();
+  plan->nchunks = nchunks;
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
@@ -1332,10 +1473,12 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
 }
 
 extern "C" uint32_t ntt_plan_task_count(uint32_t da, uint32_t db) {
-  int n = ceil_log2((uint64_t)da + db + 1);
-  if (n <= kRowLog) return 1;
-  uint32_t ntiles = 1u << (kRowLog - col_lc(n));
-  return 3 * ntiles + (1u << (n - kRowLog));
+  if ((uint64_t)da + db + 1 > ((uint64_t)1 << 31)) return 0;
+  const int n = ceil_log2((uint64_t)da + db + 1);
+  uint32_t m = 0;
+  int nt = 0;
+  if (split_rule(da, db, n, m, nt)) return product_tasks(n - 1) + product_tasks(nt);
+  return product_tasks(n);
 }
 
 extern "C" mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, uint32_t* ntasks,
@@ -1374,6 +1517,9 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   uint32_t gsz = grid > 0 ? (uint32_t)grid : (uint32_t)persistent_grid();
   gsz = std::max(1u, std::min(gsz, plan->ntasks));
   launch_persistent(g, gsz, s);
+  if (plan->nfix > 0)
+    hipLaunchKernelGGL(k_split_fix, dim3(std::min(plan->nchunks, 8192u)), dim3(256), 0, s, plan->d_fix, plan->nfix,
+                       plan->nchunks, d_out, static_cast<const uint32_t*>(scr));
   return last_launch_status();
 }
 

@@ -366,3 +366,76 @@ def test_batch_unaligned_offsets(N, ctx):
         P = PRIMES[pid[i]]
         ref = oracle.polymul(P, coeffs[a_off[i]: a_off[i] + da[i] + 1], coeffs[b_off[i]: b_off[i] + db[i] + 1])
         assert np.array_equal(got[c_off[i]: c_off[i] + ref.size], ref), i
+
+
+# Shapes around the split rule: a product of length L just above N/2 = h runs
+# as its cyclic part of length h plus the product of the top m = L - h
+# coefficients of each operand, joined by a fix-up kernel after the launch.
+SPLIT_SHAPES = [(1, 1), (2, 1), (2, 2), (4, 4), (16, 16), (32, 31), (33, 30), (64, 64), (100, 60),
+                (2048, 2048), (2049, 2047), (4096, 4096), (4100, 4100), (4097, 4095), (4095, 4097),
+                (5000, 3300), (6000, 6000), (8192, 8192), (8200, 8200), (8191, 100), (16384, 10),
+                (9000, 9100), (20000, 20000), (40000, 30000), (70000, 70000), (65600, 65400),
+                ((1 << 19) + 3, (1 << 19) + 1), ((1 << 20) + 100, (1 << 20) - 100), (300000, 900)]
+
+
+def test_split_rule_is_used(N):
+    """The plan splits products just above a power of two (fewer tasks than
+    the plain two-pass product) and leaves the others whole."""
+    assert N.task_count(4100, 4100) == 2            # 2^13 cyclic + a 32-point top product
+    assert N.task_count(20000, 20000) < 3 * 4 + 8   # below the unsplit 2^16 product's 3 ntiles + nblocks
+    assert N.task_count(6000, 6000) == N.task_count(8191, 8191)   # m too large to pay: unsplit
+
+
+def test_batch_split_shapes_vs_oracle(N, ctx):
+    rng = np.random.default_rng(77)
+    da = [s[0] for s in SPLIT_SHAPES]
+    db = [s[1] for s in SPLIT_SHAPES]
+    pid = rng.integers(0, len(PRIMES), len(da))
+    batch = wl.pack_products(PRIMES, pid, da, db, rng)
+    ref = oracle_batch(batch)
+    outs = []
+    for grid, seed in [(0, 0), (5, 31337)]:
+        st, got = run_plan(N, ctx, batch, grid=grid, order_seed=seed)
+        assert st == 0
+        for i in range(batch.count):
+            c0, n = int(batch.c_off[i]), int(batch.da[i] + batch.db[i] + 1)
+            assert np.array_equal(got[c0:c0 + n], ref[c0:c0 + n]), (grid, seed, SPLIT_SHAPES[i])
+        outs.append(got)
+    assert outs[0].tobytes() == outs[1].tobytes()
+
+
+def test_split_special_values(N, ctx):
+    """All-(P-1) operands, whose top coefficients are largest, and the binomial
+    square (1+x)^d (1+x)^d = (1+x)^2d, at split lengths."""
+    def binomials_mod(n, P):
+        """C(n, k) mod P for k = 0 .. n from factorials mod P (n < P)."""
+        f = [1] * (n + 1)
+        for i in range(1, n + 1):
+            f[i] = f[i - 1] * i % P
+        inv_fn = pow(f[n], P - 2, P)
+        inv = [1] * (n + 1)
+        inv[n] = inv_fn
+        for i in range(n, 0, -1):
+            inv[i - 1] = inv[i] * i % P
+        return [f[n] * inv[k] % P * inv[n - k] % P for k in range(n + 1)]
+
+    for d in (4100, 20000, 65600):
+        P = PRIMES[d % len(PRIMES)]
+        full = np.full(d + 1, P - 1, dtype=np.uint32)
+        b = wl.pack_products(PRIMES, [PRIMES.index(P)], [d], [d], np.random.default_rng(0))
+        b.coeffs[b.a_off[0]:b.a_off[0] + d + 1] = full
+        b.coeffs[b.b_off[0]:b.b_off[0] + d + 1] = full
+        st, got = run_plan(N, ctx, b)
+        assert st == 0
+        k = np.arange(2 * d + 1, dtype=np.int64)
+        want = ((np.minimum(k, 2 * d - k) + 1) % P).astype(np.uint64)   # (P-1)^2 = 1 mod P
+        assert np.array_equal(got[:2 * d + 1].astype(np.uint64), want)
+        binom = np.array(binomials_mod(d, P), dtype=np.uint32)
+        b.coeffs[b.a_off[0]:b.a_off[0] + d + 1] = binom
+        b.coeffs[b.b_off[0]:b.b_off[0] + d + 1] = binom
+        st, got = run_plan(N, ctx, b)
+        assert st == 0
+        idx = np.unique(np.concatenate([np.arange(0, 2 * d + 1, 997), np.arange(2 * d - 40, 2 * d + 1),
+                                        np.arange(40), [1 << (2 * d).bit_length() - 1]]))
+        c2 = binomials_mod(2 * d, P)
+        assert all(int(got[i]) == c2[int(i)] for i in idx)
