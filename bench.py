@@ -475,7 +475,10 @@ def polymul_batch_extra(torch, wl, dev):
     din = torch.from_numpy(batch.coeffs.view(np.int32)).to(dev)
     dout = torch.empty(batch.out_len, dtype=torch.int32, device=dev)
     scr = plan.alloc_scratch()
+    # algorithmic count at each product's power-of-two length; the plan may
+    # split products and execute fewer (ntt_plan_work)
     redc = sum(polymul_redc_count(int(a), int(b)) for a, b in zip(batch.da, batch.db))
+    executed, nsplit = plan.work()
     t_batch = timed(torch, lambda: plan.execute(din, dout, scr), 5)
     st = plan.status(scr)
     got = dout.cpu().numpy().view(np.uint32)
@@ -518,7 +521,8 @@ def polymul_batch_extra(torch, wl, dev):
            "polymul_per_s_plain": round(batch.count / t_plain, 1),
            "speedup_vs_plain": round(t_plain / t_batch, 2),
            "Gredc_per_s": round(redc / t_batch / 1e9, 2), "redc_per_batch": int(redc),
-           "tasks": plan.ntasks, "grid": plan.default_grid}
+           "redc_executed_per_batch": int(executed), "Gredc_per_s_executed": round(executed / t_batch / 1e9, 2),
+           "split_products": int(nsplit), "tasks": plan.ntasks, "grid": plan.default_grid}
     log("polymul batch: %s" % res)
     del g
     plan.close()

@@ -151,6 +151,12 @@ MONT_API mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs, 
 MONT_API mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, uint32_t* ntasks,
                                    uint64_t* in_words, uint64_t* out_words, int* default_grid);
 
+/* The work one execution of the plan performs: REDC operations (three
+ * transforms of (N/2) log2 N butterflies, N pointwise products and db+1
+ * operand scalings per product as planned, after splitting) and the number
+ * of split products.  Either output pointer may be NULL. */
+MONT_API mont_status ntt_plan_work(const ntt_plan* plan, uint64_t* redc, uint32_t* split_products);
+
 /*
  * ntt_plan_execute -- zeroes the scratch header with a fill kernel, then runs
  * the whole batch in one persistent launch of `grid` workgroups (0 = the

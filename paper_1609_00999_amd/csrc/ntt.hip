@@ -897,6 +897,7 @@ struct ntt_plan {
   uint2* d_tasks = nullptr;
   uint32_t nfix = 0;        // split products (count above counts their two parts)
   uint32_t nchunks = 0;     // fix-up chunks
+  uint64_t redc = 0;        // REDC one execution performs
   FixDev* d_fix = nullptr;
   int default_grid = 0;
   // Reusable plans (ntt_plan_reserve): device capacity and pinned staging
@@ -1239,8 +1240,10 @@ uint32_t product_tasks(int n) {
 // product, then 2N words per multi-pass product and the top parts' outputs.
 mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count, uint32_t order_seed,
                        std::vector<ProdDev>& prods, std::vector<uint2>& tasks, std::vector<FixDev>& fixes,
-                       uint32_t& nchunks, uint64_t& scr_words, uint64_t& in_words, uint64_t& out_words) {
+                       uint32_t& nchunks, uint64_t& scr_words, uint64_t& in_words, uint64_t& out_words,
+                       uint64_t& redc) {
   nchunks = 0;
+  redc = 0;
   prods.clear();
   prods.reserve(2 * (size_t)count);
   fixes.clear();
@@ -1299,6 +1302,9 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
     }
   }
   const int np = (int)prods.size();
+  // Executed REDC: three transforms of (N/2) n butterflies, N pointwise
+  // products and db + 1 scalings of b per internal product.
+  for (const ProdDev& pd : prods) redc += 3ull * (1ull << pd.n) / 2 * pd.n + (1ull << pd.n) + pd.db + 1;
   uint64_t scr = kHdrWords + 2ull * np;
   scr = (scr + 63) & ~63ull;
   for (int p = 0, f = 0; p < np; p++) {
@@ -1373,7 +1379,9 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
   std::vector<FixDev> fixes;
   uint64_t scr = 0, in_words = 0, out_words = 0;
   uint32_t nchunks = 0;
-  mont_status st = build_plan(ctx, descs, count, order_seed, prods, tasks, fixes, nchunks, scr, in_words, out_words);
+  uint64_t redc = 0;
+  mont_status st = build_plan(ctx, descs, count, order_seed, prods, tasks, fixes, nchunks, scr, in_words, out_words,
+                              redc);
   if (st != MONT_OK) return st;
   ntt_plan* plan = new (std::nothrow) ntt_plan;
   if (!plan) return MONT_ENOMEM;
@@ -1382,6 +1390,7 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
   plan->ntasks = (uint32_t)tasks.size();
   plan->nfix = (uint32_t)fixes.size();
   plan->nchunks = nchunks;
+  plan->redc = redc;
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
@@ -1440,8 +1449,9 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   std::vector<FixDev> fixes;
   uint64_t scr = 0, in_words = 0, out_words = 0;
   uint32_t nchunks = 0;
+  uint64_t redc = 0;
   mont_status st = build_plan(plan->ctx, descs, count, order_seed, prods, tasks, fixes, nchunks, scr, in_words,
-                              out_words);
+                              out_words, redc);
   if (st != MONT_OK) return st;
   if (tasks.size() > plan->cap_tasks) return MONT_ERANGE;
   // The previous upload must have finished reading the staging buffers.
@@ -1466,6 +1476,7 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   plan->ntasks = (uint32_t)tasks.size();
   plan->nfix = (uint32_t)fixes.size();
   plan->nchunks = nchunks;
+  plan->redc = redc;
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
@@ -1489,6 +1500,13 @@ extern "C" mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes
   if (in_words) *in_words = plan->in_words;
   if (out_words) *out_words = plan->out_words;
   if (default_grid) *default_grid = persistent_grid();
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_plan_work(const ntt_plan* plan, uint64_t* redc, uint32_t* split_products) {
+  if (!plan) return MONT_EINVAL;
+  if (redc) *redc = plan->redc;
+  if (split_products) *split_products = plan->nfix;
   return MONT_OK;
 }
 

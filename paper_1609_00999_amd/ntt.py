@@ -47,6 +47,7 @@ def register(L) -> None:
     L.ntt_polymul.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp, c_u32, c_vp, c_vp, c_size, c_vp]
     L.ntt_plan_create.argtypes = [c_vp, c_vp, c_int, c_u32, vpp]
     L.ntt_plan_reserve.argtypes = [c_vp, c_int, c_u32, vpp]
+    L.ntt_plan_work.argtypes = [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_u32)]
     L.ntt_plan_task_count.argtypes = [c_u32, c_u32]
     L.ntt_plan_task_count.restype = c_u32
     L.ntt_plan_update.argtypes = [c_vp, c_vp, c_int, c_u32, c_vp]
@@ -218,6 +219,12 @@ class Plan:
         mont.check(mont.lib().ntt_plan_update(self.handle, descs.ctypes.data if len(descs) else None, len(descs),
                                               order_seed, mont.stream_handle()), "ntt_plan_update")
         self._info()
+
+    def work(self):
+        """(REDC per execution as planned, number of split products)."""
+        r, sp = c_u64(), c_u32()
+        mont.check(mont.lib().ntt_plan_work(self.handle, ctypes.byref(r), ctypes.byref(sp)), "ntt_plan_work")
+        return r.value, sp.value
 
     def _info(self):
         sb, nt, iw, ow, g = c_size(), c_u32(), c_u64(), c_u64(), c_int()

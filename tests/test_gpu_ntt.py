@@ -439,3 +439,32 @@ def test_split_special_values(N, ctx):
                                         np.arange(40), [1 << (2 * d).bit_length() - 1]]))
         c2 = binomials_mod(2 * d, P)
         assert all(int(got[i]) == c2[int(i)] for i in idx)
+
+
+def test_plan_work_counts(N, ctx):
+    """ntt_plan_work reports the REDC of the products as planned: the split
+    rule (multi-pass product, both operands below h = N/2, top product of
+    length <= N/4) restated here, and three transforms, N pointwise products
+    and db+1 scalings per planned product."""
+    def cost(n, db):
+        return 3 * (1 << n) // 2 * n + (1 << n) + db + 1
+
+    rng = np.random.default_rng(5)
+    da = [s[0] for s in SPLIT_SHAPES]
+    db = [s[1] for s in SPLIT_SHAPES]
+    batch = wl.pack_products(PRIMES, rng.integers(0, len(PRIMES), len(da)), da, db, rng)
+    want, nsplit = 0, 0
+    for a, b in zip(da, db):
+        L = a + b + 1
+        n = (L - 1).bit_length()
+        h = 1 << (n - 1)
+        m = L - h
+        if n > 13 and a + 1 <= h and b + 1 <= h and (2 * m - 2).bit_length() <= n - 2:
+            want += cost(n - 1, b) + cost((2 * m - 2).bit_length(), m - 1)
+            nsplit += 1
+        else:
+            want += cost(n, b)
+    plan = N.Plan.from_batch(ctx, batch)
+    assert plan.work() == (want, nsplit)
+    assert nsplit > 0
+    plan.close()
