@@ -47,6 +47,40 @@ __device__ __forceinline__ uint32_t pow_win2(uint32_t x, uint32_t e, Mod md, uin
   return r;
 }
 
+// REDC without its final subtraction: for T < R P, t = (T + m P) / R lies in
+// [0, 2P).  When 4P < R, operands in [0, 2P) keep T < 4P^2 < R P, so a chain
+// of such products stays in [0, 2P) and one conditional subtraction at its
+// end makes the result canonical.  Three instructions instead of five.
+__device__ __forceinline__ uint32_t mmul_lazy(uint32_t a, uint32_t b, Mod md) {
+  const uint64_t T = (uint64_t)a * b;
+  const uint32_t m = (uint32_t)T * md.Pp;
+  return (uint32_t)(((uint64_t)m * md.P + T) >> 32);
+}
+
+// pow_win2 for P < 2^30 with lazy products: the window table and the running
+// power stay in [0, 2P) and are reduced once at the end.
+__device__ __forceinline__ uint32_t pow_win2_lazy(uint32_t x, uint32_t e, Mod md, uint32_t one) {
+  uint32_t x2 = mmul_lazy(x, x, md);
+  uint32_t x3 = mmul_lazy(x2, x, md);
+  auto pick = [&](uint32_t d) {
+    uint32_t lo = (d & 1u) ? x : one;
+    uint32_t hi = (d & 1u) ? x3 : x2;
+    return (d & 2u) ? hi : lo;
+  };
+  uint32_t r = pick(e >> 30);
+#pragma unroll
+  for (int s = 28; s >= 0; s -= 2) {
+    r = mmul_lazy(r, r, md);
+    r = mmul_lazy(r, r, md);
+    r = mmul_lazy(r, pick((e >> s) & 3u), md);
+  }
+  const uint32_t u = r - md.P;
+  return u < r ? u : r;
+}
+
+// Operation for the lazy power; shares OP_POW's launch shape.
+constexpr int OP_POW_LAZY = OP_COUNT;
+
 // Scalar operation applied per element.
 template <int OP>
 __device__ __forceinline__ uint32_t elem_op(uint32_t a, uint32_t b, uint32_t c, Mod md, uint32_t kc) {
@@ -54,6 +88,7 @@ __device__ __forceinline__ uint32_t elem_op(uint32_t a, uint32_t b, uint32_t c, 
   else if constexpr (OP == OP_FROM) return redc((uint64_t)a, md); // REDC(a * 1)
   else if constexpr (OP == OP_MUL) return mmul(a, b, md);
   else if constexpr (OP == OP_MULADD) return madd(mmul(a, b, md), c, md.P);
+  else if constexpr (OP == OP_POW_LAZY) return pow_win2_lazy(a, b, md, kc);
   else return pow_win2(a, b, md, kc);                             // kc = residue of 1
 }
 
@@ -198,7 +233,10 @@ mont_status run(int op, const mont_params* prm, const uint32_t* a, const uint32_
     case OP_FROM: dispatch<OP_FROM>(t, md, 0, a, nullptr, nullptr, out, n, s); break;
     case OP_MUL: dispatch<OP_MUL>(t, md, 0, a, b, nullptr, out, n, s); break;
     case OP_MULADD: dispatch<OP_MULADD>(t, md, 0, a, b, c, out, n, s); break;
-    default: dispatch<OP_POW>(t, md, prm->R1, a, b, nullptr, out, n, s); break;
+    default:
+      if (prm->P < (1u << 30)) dispatch<OP_POW_LAZY>(t, md, prm->R1, a, b, nullptr, out, n, s);
+      else dispatch<OP_POW>(t, md, prm->R1, a, b, nullptr, out, n, s);
+      break;
   }
   return last_launch_status();
 }

@@ -274,3 +274,19 @@ def test_checked_mode(M):
     assert M.checked_status() == 0
     with pytest.raises(M.MontError):
         M.check_range(0, dev(a), torch.zeros(1, dtype=torch.int32, device="cuda"))
+
+
+@pytest.mark.parametrize("P", [3, 5, 15, 17, 65537, 469762049, 998244353, (1 << 30) - 35, (1 << 30) - 1,
+                               (1 << 30) + 1, (1 << 30) + 3, 2013265921, 2147483647])
+def test_pow_both_reduction_paths(M, P):
+    """Powers for moduli on both sides of 2^30: below it the power chain keeps
+    its values in [0, 2P) and reduces once at the end; above it every product
+    is reduced.  Edge bases and exponents, against the oracle."""
+    prm = M.setup(P)
+    rng = np.random.default_rng(P % 65521)
+    e = edge_values(P)
+    base = np.concatenate([np.repeat(e, 8), rng.integers(0, P, 30000, dtype=np.uint32)])
+    ex = rng.integers(0, 1 << 32, base.size, dtype=np.uint64).astype(np.uint32)
+    ex[: 8 * e.size] = np.tile(np.array([0, 1, 2, 3, 0xFFFFFFFF, 0xAAAAAAAA, 0x55555555, P - 1], dtype=np.uint64)
+                               .astype(np.uint32), e.size)
+    assert np.array_equal(host(M.pow(prm, dev(base), dev(ex))), oracle.mont_pow(P, base, ex))
