@@ -179,6 +179,11 @@ def main():
                      "frac_of_same_traffic_add": round(achieved / ref["torch_add_int32"]["GB_per_s"], 4)},
     }
 
+    props = torch.cuda.get_device_properties(dev)
+    result["device"] = {"name": props.name, "arch": getattr(props, "gcnArchName", ""),
+                        "compute_units": props.multi_processor_count,
+                        "hbm_gib": round(props.total_memory / 2 ** 30, 1)}
+
     if args.copy_calibration:
         x = sets[0][1]
         y = torch.empty_like(x)
@@ -446,6 +451,13 @@ def serving_extra(torch, wl, dev, count=SERVE_REQUESTS + SERVE_WARMUP, rate=SERV
     plain = serve.GpuPlainExecutor(ctx, inputs, keep_results=False)
     pst = serve.Scheduler(plain, slots=1, budget_bytes=budget, max_batch=1).run(serve.jobs_from_requests(reqs))
     res["plain_launches"] = pst.summary(warmup)
+    # modular products served per second: n per elementwise request, the
+    # power-of-two algorithmic REDC count per polynomial product
+    work = sum(r.size if r.kind == "mul" else polymul_redc_count(r.size, r.size) for r in reqs[warmup:])
+    for key in ("batched", "plain_launches"):
+        w = res[key].get("wall_s")
+        if w:
+            res[key]["Gmodmul_per_s_served"] = round(work / w / 1e9, 2)
     b, p = res["batched"], res["plain_launches"]
     if b.get("p99_ms") and p.get("p99_ms"):
         res["p99_speedup_vs_plain"] = round(p["p99_ms"] / b["p99_ms"], 2)
