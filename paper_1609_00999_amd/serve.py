@@ -63,6 +63,8 @@ class RunStats:
     batches: int
     max_inflight_bytes: int
     batch_sizes: list = field(default_factory=list)
+    launch_s: list = field(default_factory=list)      # host time spent in each executor launch
+    launch_first_rid: list = field(default_factory=list)   # first request id of each launched batch
 
     def latencies(self, kind=None, warmup: int = 0):
         return np.array([j.latency for j in self.jobs[warmup:] if j.status == OK and (kind is None or j.kind == kind)])
@@ -85,6 +87,14 @@ class RunStats:
                     out["p99_ms_" + kind] = round(float(np.percentile(lk, 99)) * 1e3, 3)
         if self.batch_sizes:
             out["mean_batch"] = round(float(np.mean(self.batch_sizes)), 2)
+        if self.launch_s:
+            ls = np.array([t for t, r in zip(self.launch_s, self.launch_first_rid) if r >= warmup]
+                          if len(self.launch_first_rid) == len(self.launch_s) else self.launch_s)
+            if ls.size == 0:
+                ls = np.array(self.launch_s)
+            out["launch_ms_p50"] = round(float(np.percentile(ls, 50)) * 1e3, 3)
+            out["launch_ms_max"] = round(float(ls.max()) * 1e3, 3)
+            out["launches_over_1ms"] = int((ls > 1e-3).sum())
         counts = collections.Counter(STATUS_NAMES.get(j.status, "?") for j in self.jobs[warmup:])
         out["status_counts"] = dict(counts)
         return out
@@ -116,6 +126,8 @@ class Scheduler:
         max_used = 0
         batches = 0
         sizes = []
+        launch_s = []
+        launch_rid = []
         nxt = 0
         t0 = self.clock()
         while nxt < len(jobs) or pending or inflight:
@@ -174,6 +186,8 @@ class Scheduler:
                 for j in batch:
                     j.t_admit = t_admit
                 handle = self.ex.launch(slot, batch)
+                launch_s.append(self.clock() - t0 - t_admit)
+                launch_rid.append(min(j.rid for j in batch))
                 inflight[slot] = (handle, batch, fp)
                 used += fp
                 max_used = max(max_used, used)
@@ -182,7 +196,7 @@ class Scheduler:
                 progressed = True
             if not progressed and self.idle_sleep > 0:
                 time.sleep(self.idle_sleep)
-        return RunStats(jobs, self.clock() - t0, batches, max_used, sizes)
+        return RunStats(jobs, self.clock() - t0, batches, max_used, sizes, launch_s, launch_rid)
 
 
 # ---------------------------------------------------------------------------
@@ -211,6 +225,7 @@ class DeviceInputs:
             pos = (pos + 3) & ~3            # keep every operand 16-byte aligned
         self.arena = torch.empty(max(4, pos), dtype=torch.int32, device=device)
         self.offs = offs
+        self.kinds = {r.rid: r.kind for r in reqs}
         self.primes = primes
         gen = torch.Generator(device=device)
         for r in reqs:
@@ -236,7 +251,7 @@ class GpuBatchExecutor:
     requests and one for its polynomial products, on the slot's stream."""
 
     def __init__(self, ctx, inputs: DeviceInputs, slots: int, max_batch: int, keep_results: bool = True,
-                 max_tasks: int = 1 << 20):
+                 max_tasks: int = 1 << 20, arena_bytes: int = 1 << 30):
         import torch
         from . import mont, ntt
         self.torch, self.mont, self.ntt = torch, mont, ntt
@@ -248,6 +263,28 @@ class GpuBatchExecutor:
         self.vecb = [mont.Batch(max_batch) for _ in range(slots)]
         self.plans = [ntt.Plan.reserve(ctx, max_batch, max_tasks) for _ in range(slots)]
         self.max_tasks = max_tasks
+        dev = inputs.arena.device
+        # Per-slot device arenas: a batch carves its outputs and transform
+        # scratch from its slot's arena (a slot runs one batch at a time), so
+        # the request loop makes no allocator calls; a batch larger than the
+        # arena falls back to torch allocations and is counted.
+        self.arena_words = max(1024, arena_bytes // 4)
+        self.arenas = [torch.empty(self.arena_words, dtype=torch.int32, device=dev) for _ in range(slots)]
+        self.fallback_batches = 0
+        # Results that are kept are copied out of the arena when their batch
+        # finishes, into space reserved here for a known set of requests.
+        self.kept = {}
+        if isinstance(keep_results, (set, frozenset)):
+            words = {rid: self._result_words(rid) for rid in keep_results}
+            pool = torch.empty(max(1, sum(_a4(w) for w in words.values())), dtype=torch.int32, device=dev)
+            pos = 0
+            for rid, w in sorted(words.items()):
+                self.kept[rid] = pool[pos:pos + w]
+                pos += _a4(w)
+
+    def _result_words(self, rid) -> int:
+        _, _, n = self.inputs.offs[rid]       # n residues, or d + 1 coefficients
+        return n if self.inputs.kinds[rid] == "mul" else 2 * n - 1
 
     def footprint(self, job: Job) -> int:
         if job.kind == "mul":
@@ -260,13 +297,38 @@ class GpuBatchExecutor:
         s = self.streams[slot]
         muls = [j for j in batch if j.kind == "mul"]
         polys = [j for j in batch if j.kind == "polymul"]
-        keep = []
+        dev = self.inputs.arena.device
         with torch.cuda.stream(s):
+            plan, desc, cpos = None, None, 0
+            if polys:
+                desc = np.zeros(len(polys), dtype=ntt.DESC_DTYPE)
+                for i, j in enumerate(polys):
+                    a0, b0, n = self.inputs.offs[j.rid]
+                    desc[i] = (j.prime_id, j.size, j.size, 0, a0, b0, cpos)
+                    cpos += 2 * j.size + 1
+                plan = self.plans[slot]
+                plan.update(desc)
+            scr_words = (plan.scratch_bytes + 3) // 4 if plan is not None else 0
+            need = sum(_a4(j.size) for j in muls) + (_a4(cpos) + _a4(scr_words) if polys else 0)
+            arena = self.arenas[slot] if need <= self.arena_words else None
+            if arena is None:
+                self.fallback_batches += 1
+            pos = 0
+
+            def take(nw):
+                nonlocal pos
+                if arena is None:
+                    return torch.empty(max(1, nw), dtype=torch.int32, device=dev)
+                v = arena[pos:pos + max(1, nw)]
+                pos += _a4(max(1, nw))
+                return v
+
+            keep = []
             if muls:
                 descs = (mont.VecDesc * len(muls))()
                 for i, j in enumerate(muls):
                     a, b = self.inputs.views(j.rid)
-                    out = torch.empty(j.size, dtype=torch.int32, device=a.device)
+                    out = take(j.size)
                     prm = self.params[j.prime_id]
                     descs[i] = mont.VecDesc(a.data_ptr(), b.data_ptr(), out.data_ptr(), j.size, prm.P, prm.Pprime)
                     j.result = out
@@ -274,17 +336,8 @@ class GpuBatchExecutor:
                 self.vecb[slot].update_raw(descs)
                 self.vecb[slot].mul()
             if polys:
-                desc = np.zeros(len(polys), dtype=ntt.DESC_DTYPE)
-                cpos = 0
-                for i, j in enumerate(polys):
-                    a0, b0, n = self.inputs.offs[j.rid]
-                    desc[i] = (j.prime_id, j.size, j.size, 0, a0, b0, cpos)
-                    cpos += 2 * j.size + 1
-                plan = self.plans[slot]
-                plan.update(desc)
-                out = torch.empty(max(1, cpos), dtype=torch.int32, device=self.inputs.arena.device)
-                scr = torch.empty(max(1, (plan.scratch_bytes + 3) // 4), dtype=torch.int32,
-                                  device=self.inputs.arena.device)
+                out = take(cpos)
+                scr = take(scr_words)
                 plan.execute(self.inputs.arena, out, scr)
                 keep += [out, scr]
                 for i, j in enumerate(polys):
@@ -292,16 +345,23 @@ class GpuBatchExecutor:
                     j.result = out[c0:c0 + 2 * j.size + 1]
             ev = torch.cuda.Event()
             ev.record(s)
-        return (ev, batch, keep)
+        return (ev, batch, keep, slot, arena is not None)
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle) -> dict:
-        ev, batch, keep = handle
+        ev, batch, keep, slot, in_arena = handle
+        torch = self.torch
         for j in batch:
             if not _keeps(self.keep, j.rid):
                 j.result = None
+            elif in_arena:
+                # The slot's next batch reuses the arena: copy on the slot's
+                # stream, so the copy is ordered before that batch.
+                with torch.cuda.stream(self.streams[slot]):
+                    dst = self.kept.get(j.rid)
+                    j.result = dst.copy_(j.result) if dst is not None else j.result.clone()
         return {}
 
     def close(self):
@@ -309,6 +369,12 @@ class GpuBatchExecutor:
             b.close()
         for p in self.plans:
             p.close()
+        self.arenas = []
+
+
+def _a4(words: int) -> int:
+    """Words rounded up to a multiple of 4 (16-byte alignment for vector access)."""
+    return (int(words) + 3) & ~3
 
 
 class GpuPlainExecutor:

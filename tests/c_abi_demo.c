@@ -1,0 +1,179 @@
+/*
+ * c_abi_demo.c -- libmont used from plain C through its headers only: no
+ * Python, no torch.  Built by tests/test_c_abi.py with gcc against
+ * include/*.h, linked with libmont.so, the HIP runtime and the CPU oracle
+ * (test infrastructure).
+ *
+ *   c_abi_demo host   -- host-only calls: section 3.1 precomputation, the CRT
+ *                        constants and error statuses (no GPU needed);
+ *   c_abi_demo device -- device buffers from hipMalloc: conversion, product
+ *                        and mul-add chains, a polynomial product and 64-bit
+ *                        products, each compared with the oracle.
+ * Prints one line per check and exits 0 only if all pass.
+ */
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "mont.h"
+#include "mont64.h"
+#include "mont_crt.h"
+#include "mont_ntt.h"
+
+/* oracle (liboracle.so) */
+int orc_setup(uint32_t P, int r, uint32_t out[5]);
+void orc_muladd(uint32_t P, uint32_t Rinv, const uint32_t* a, const uint32_t* b, const uint32_t* c, uint32_t* out,
+                size_t n);
+void orc_polymul_schoolbook(uint32_t P, const uint32_t* a, uint32_t da, const uint32_t* b, uint32_t db, uint32_t* c);
+int orc64_setup(uint64_t P, int r, uint64_t out[5]);
+void orc64_mul(uint64_t P, uint64_t Rinv, const uint64_t* a, const uint64_t* b, uint64_t* out, size_t n);
+
+static int failures = 0;
+
+static void check(int ok, const char* what) {
+  printf("%s %s\n", ok ? "ok  " : "FAIL", what);
+  if (!ok) failures++;
+}
+
+/* xorshift64: the demo's own input generator */
+static uint64_t rs = 88172645463325252ull;
+static uint64_t next64(void) {
+  rs ^= rs << 13;
+  rs ^= rs >> 7;
+  rs ^= rs << 17;
+  return rs;
+}
+
+static int host_checks(void) {
+  mont_params p;
+  uint32_t ref[5];
+  check(mont_setup(998244353u, &p) == MONT_OK && orc_setup(998244353u, 32, ref) == 0 && p.Pprime == ref[0] &&
+            p.R1 == ref[1] && p.R2 == ref[2] && p.k == ref[4],
+        "mont_setup(998244353) matches the oracle");
+  check(p.P * p.Pprime == 0xFFFFFFFFu, "P P' = -1 mod 2^32");
+  check(mont_setup(4u, &p) == MONT_EINVAL && mont_setup(0x80000001u, &p) == MONT_EINVAL, "even / too large P");
+  check(strlen(mont_strerror(MONT_ENOROOT)) > 0, "mont_strerror");
+  mont64_params q;
+  uint64_t ref64[5];
+  check(mont64_setup(9223372036854775783ull, &q) == MONT_OK && orc64_setup(9223372036854775783ull, 64, ref64) == 0 &&
+            q.Pprime == ref64[0] && q.R1 == ref64[1] && q.R2 == ref64[2],
+        "mont64_setup(2^63 - 25) matches the oracle");
+  crt_params c;
+  const uint32_t primes[3] = {2013265921u, 1811939329u, 2113929217u};
+  check(crt_setup(primes, &c) == MONT_OK && c.P[2] == primes[2], "crt_setup");
+  const uint32_t bad[3] = {2013265921u, 2013265921u, 2113929217u};
+  check(crt_setup(bad, &c) == MONT_EINVAL, "crt_setup rejects a repeated prime");
+  check(mont_mul(&p, NULL, NULL, NULL, 0, NULL) == MONT_OK, "n = 0 enqueues nothing");
+  check(ntt_polymul_scratch_bytes(100, 100) == 0 && ntt_polymul_scratch_bytes(10000, 10000) == ((size_t)8 << 15),
+        "ntt_polymul_scratch_bytes");
+  return failures;
+}
+
+#define HIP_OK(x)                                              \
+  do {                                                         \
+    if ((x) != hipSuccess) {                                   \
+      printf("FAIL hip call %s\n", #x);                         \
+      return 1;                                                \
+    }                                                          \
+  } while (0)
+
+static int device_checks(void) {
+  const uint32_t P = 2013265921u;
+  const size_t n = 100003;
+  mont_params p;
+  uint32_t ref[5];
+  if (mont_setup(P, &p) != MONT_OK || orc_setup(P, 32, ref) != 0) return 1;
+  uint32_t *ha = malloc(4 * n), *hb = malloc(4 * n), *hc = malloc(4 * n), *hout = malloc(4 * n),
+           *want = malloc(4 * n);
+  for (size_t i = 0; i < n; i++) {
+    ha[i] = (uint32_t)(next64() % P);
+    hb[i] = (uint32_t)(next64() % P);
+    hc[i] = (uint32_t)(next64() % P);
+  }
+  uint32_t *da, *db, *dc, *dout;
+  HIP_OK(hipMalloc((void**)&da, 4 * n));
+  HIP_OK(hipMalloc((void**)&db, 4 * n));
+  HIP_OK(hipMalloc((void**)&dc, 4 * n));
+  HIP_OK(hipMalloc((void**)&dout, 4 * n));
+  HIP_OK(hipMemcpy(da, ha, 4 * n, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(db, hb, 4 * n, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(dc, hc, 4 * n, hipMemcpyHostToDevice));
+  hipStream_t s;
+  HIP_OK(hipStreamCreate(&s));
+
+  /* a*b mod P through residues: to, to, mul, from */
+  check(mont_to(&p, da, dout, n, s) == MONT_OK && mont_to(&p, db, dc, n, s) == MONT_OK &&
+            mont_mul(&p, dout, dc, dout, n, s) == MONT_OK && mont_from(&p, dout, dout, n, s) == MONT_OK,
+        "enqueue to/to/mul/from");
+  HIP_OK(hipMemcpyAsync(hout, dout, 4 * n, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  int ok = 1;
+  for (size_t i = 0; i < n && ok; i++) ok = hout[i] == (uint32_t)(((uint64_t)ha[i] * hb[i]) % P);
+  check(ok, "from(mul(to a, to b)) = a b mod P for 100003 pairs");
+
+  /* mul-add on residues, in place on c */
+  HIP_OK(hipMemcpy(dc, hc, 4 * n, hipMemcpyHostToDevice));
+  check(mont_muladd(&p, da, db, dc, dc, n, s) == MONT_OK, "enqueue mul-add");
+  HIP_OK(hipMemcpyAsync(hout, dc, 4 * n, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  orc_muladd(P, ref[3], ha, hb, hc, want, n);
+  check(memcmp(hout, want, 4 * n) == 0, "mont_muladd matches the oracle");
+
+  /* a polynomial product of degrees 3000 and 2000 */
+  ntt_ctx* ctx = NULL;
+  const uint32_t pr[1] = {P};
+  check(ntt_ctx_create(pr, 1, 16, &ctx) == MONT_OK, "ntt_ctx_create");
+  const uint32_t dA = 3000, dB = 2000;
+  check(ntt_polymul(ctx, 0, da, dA, db, dB, dout, NULL, 0, s) == MONT_OK, "enqueue ntt_polymul");
+  HIP_OK(hipMemcpyAsync(hout, dout, 4 * (dA + dB + 1), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  orc_polymul_schoolbook(P, ha, dA, hb, dB, want);
+  check(memcmp(hout, want, 4 * (dA + dB + 1)) == 0, "ntt_polymul matches the schoolbook product");
+  check(ntt_polymul(ctx, 0, da, 20000, db, 20000, dout, NULL, 0, s) == MONT_ENOMEM, "missing scratch: ENOMEM");
+  ntt_ctx_destroy(ctx);
+
+  /* 64-bit residues */
+  const uint64_t Q = 9223372036854775783ull;
+  const size_t m = 50001;
+  mont64_params q;
+  uint64_t r64[5];
+  if (mont64_setup(Q, &q) != MONT_OK || orc64_setup(Q, 64, r64) != 0) return 1;
+  uint64_t *xa = malloc(8 * m), *xb = malloc(8 * m), *xo = malloc(8 * m), *xw = malloc(8 * m);
+  for (size_t i = 0; i < m; i++) {
+    xa[i] = next64() % Q;
+    xb[i] = next64() % Q;
+  }
+  uint64_t *ya, *yb;
+  HIP_OK(hipMalloc((void**)&ya, 8 * m));
+  HIP_OK(hipMalloc((void**)&yb, 8 * m));
+  HIP_OK(hipMemcpy(ya, xa, 8 * m, hipMemcpyHostToDevice));
+  HIP_OK(hipMemcpy(yb, xb, 8 * m, hipMemcpyHostToDevice));
+  check(mont64_mul(&q, ya, yb, ya, m, s) == MONT_OK, "enqueue mont64_mul");
+  HIP_OK(hipMemcpyAsync(xo, ya, 8 * m, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  orc64_mul(Q, r64[3], xa, xb, xw, m);
+  check(memcmp(xo, xw, 8 * m) == 0, "mont64_mul matches the oracle");
+
+  HIP_OK(hipFree(ya));
+  HIP_OK(hipFree(yb));
+  HIP_OK(hipFree(da));
+  HIP_OK(hipFree(db));
+  HIP_OK(hipFree(dc));
+  HIP_OK(hipFree(dout));
+  HIP_OK(hipStreamDestroy(s));
+  free(ha); free(hb); free(hc); free(hout); free(want);
+  free(xa); free(xb); free(xo); free(xw);
+  return failures;
+}
+
+int main(int argc, char** argv) {
+  if (argc < 2) {
+    fprintf(stderr, "usage: %s host|device\n", argv[0]);
+    return 2;
+  }
+  int bad = strcmp(argv[1], "host") == 0 ? host_checks() : device_checks();
+  printf("%d failures\n", bad);
+  return bad == 0 ? 0 : 1;
+}

@@ -156,3 +156,31 @@ def test_serving_under_tight_budget(mods, ctx):
         r = reqs[j.rid]
         assert np.array_equal(host(j.result), oracle_result(inputs, r))
     ex.close()
+
+
+def test_serving_arena_fallback_and_kept_set(mods, ctx):
+    """Batches carve outputs and scratch from per-slot arenas; a batch that
+    does not fit falls back to torch allocations, and results kept for a set
+    of requests are copied out of the arena before the slot is reused."""
+    serve, reqs, inputs = serve_setup(mods, ctx, count=40, seed=13)
+    # arenas too small for any batch: every batch falls back
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=2, max_batch=8, arena_bytes=4096)
+    st = serve.Scheduler(ex, slots=2, budget_bytes=1 << 30, max_batch=8).run(serve.jobs_from_requests(reqs))
+    assert ex.fallback_batches == st.batches > 0
+    for j in st.jobs:
+        assert np.array_equal(host(j.result), oracle_result(inputs, reqs[j.rid]))
+    ex.close()
+    # one slot, default arena, only some results kept: every kept result is
+    # exact although later batches reused the arena
+    keep = set(range(0, 40, 3))
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=1, max_batch=4, keep_results=keep)
+    st = serve.Scheduler(ex, slots=1, budget_bytes=1 << 30, max_batch=4).run(serve.jobs_from_requests(reqs))
+    assert ex.fallback_batches == 0 and st.batches >= 10
+    summary = st.summary()
+    assert summary["launch_ms_max"] >= summary["launch_ms_p50"] >= 0
+    for j in st.jobs:
+        if j.rid in keep:
+            assert np.array_equal(host(j.result), oracle_result(inputs, reqs[j.rid])), j.rid
+        else:
+            assert j.result is None
+    ex.close()
