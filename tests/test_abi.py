@@ -117,3 +117,51 @@ def test_ntt_host_validation(L):
     assert L.ntt_polymul_scratch_bytes(4095, 4096) == 0          # N = 2^13: one workgroup
     assert L.ntt_polymul_scratch_bytes(4096, 4096) == 8 << 14    # N = 2^14: two arrays of N words
     assert L.ntt_polymul_scratch_bytes((1 << 20) - 1, (1 << 20) - 1) == 8 << 21
+
+
+def test_validation_of_the_next_rows_without_gpu(L):
+    """64-bit residues, CRT products, the range check, Algorithms 3 and 1 and
+    plan queries reject bad arguments on the host (nothing is enqueued)."""
+    from paper_1609_00999_amd import crt, mont, mont64
+    EINVAL = mont.EINVAL
+    c_vp = ctypes.c_void_p
+    dummy = c_vp(0x10000)                       # never dereferenced: validation fails first
+    # 64-bit setup and parameter checks
+    q = mont64.setup(9223372036854775783)
+    assert (q.P * q.Pprime) % (1 << 64) == (1 << 64) - 1
+    for bad in (0, 2, 1 << 63, (1 << 64) - 1):
+        with pytest.raises(mont.MontError):
+            mont64.setup(bad)
+    bad = mont64.Mont64Params()
+    bad.P, bad.Pprime = 17, 3
+    L64 = mont64.lib()
+    assert L64.mont64_mul(ctypes.byref(bad), dummy, dummy, dummy, 8, None) == EINVAL
+    assert L64.mont64_mul(ctypes.byref(q), None, dummy, dummy, 8, None) == EINVAL
+    assert L64.mont64_pow(ctypes.byref(q), dummy, None, dummy, 8, None) == EINVAL
+    assert L64.mont64_mul(ctypes.byref(q), None, None, None, 0, None) == mont.OK     # n = 0
+    # CRT
+    Lc = crt.lib()
+    prm = crt.setup([2013265921, 1811939329, 2113929217])
+    assert Lc.crt_reduce(None, dummy, 8, dummy, dummy, dummy, None) == EINVAL
+    assert Lc.crt_reduce(ctypes.byref(prm), dummy, 8, None, dummy, dummy, None) == EINVAL
+    assert Lc.crt_combine(ctypes.byref(prm), dummy, dummy, None, 8, dummy, None) == EINVAL
+    assert Lc.crt_combine(ctypes.byref(prm), None, None, None, 0, None, None) == mont.OK
+    broken = crt.setup([2013265921, 1811939329, 2113929217])
+    broken.m[1].Pprime ^= 2                     # no longer -P^-1
+    assert Lc.crt_reduce(ctypes.byref(broken), dummy, 8, dummy, dummy, dummy, None) == EINVAL
+    # range check
+    L.mont_check_range.argtypes = [ctypes.c_uint32, c_vp, ctypes.c_size_t, c_vp, c_vp]
+    assert L.mont_check_range(0, dummy, 8, dummy, None) == EINVAL
+    assert L.mont_check_range(17, dummy, 8, None, None) == EINVAL
+    assert L.mont_check_range(17, dummy, 8, c_vp(0x10002), None) == EINVAL     # misaligned status
+    assert L.mont_check_range(17, None, 0, dummy, None) == mont.OK
+    # Algorithms 3 and 1
+    p17 = mont.setup(17)
+    assert L.mont_mul_fourier(ctypes.byref(p17), dummy, dummy, dummy, 8, None) == EINVAL   # v2(16) < 16
+    assert L.modmul_barrett(4, dummy, dummy, dummy, 8, None) == EINVAL
+    assert L.modpow_barrett(1 << 31, dummy, dummy, dummy, 8, None) == EINVAL
+    # plan queries
+    L.ntt_plan_work.argtypes = [c_vp, c_vp, c_vp]
+    assert L.ntt_plan_work(None, None, None) == EINVAL
+    L.ntt_plan_task_count.restype = ctypes.c_uint32
+    assert L.ntt_plan_task_count(0xFFFFFFFF, 0xFFFFFFFF) == 0                 # too long
