@@ -1234,6 +1234,15 @@ uint32_t product_tasks(int n) {
   return 3 * ntiles + (1u << (n - kRowLog));
 }
 
+// Groups of multi-pass products in the task pipeline of a plan.
+constexpr int kPipeGroups = 8;
+
+size_t product_task_total(const std::vector<ProdDev>& prods) {
+  size_t t = 0;
+  for (const ProdDev& pd : prods) t += pd.n > (uint32_t)kRowLog ? 3 * pd.ntiles + pd.nblocks : 1;
+  return t;
+}
+
 // Host side of planning: internal products (a product the split rule takes
 // becomes its cyclic part and its top part), the ordered task list, the
 // fix-up list and the scratch layout: header, two counters per internal
@@ -1248,7 +1257,7 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   prods.reserve(2 * (size_t)count);
   fixes.clear();
   tasks.clear();
-  std::vector<uint2> colf, small, row, coli;
+  std::vector<uint2> small;
   in_words = 0;
   out_words = 0;
   std::vector<uint32_t> top_words;                 // per fix-up: words of its top output
@@ -1325,34 +1334,70 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   }
   for (int p = 0; p < np; p++)
     if (prods[p].n <= (uint32_t)kRowLog) small.push_back(make_uint2((uint32_t)p, T_SMALL << 28));
-  // Cost order: longest products first within each group.
+  // Multi-pass products, longest first, cut into kPipeGroups groups of about
+  // equal work.  The list is a software pipeline over the groups: block b
+  // interleaves the row blocks of group b-1 (bound by the vector ALU) with the
+  // forward column tiles of group b and the inverse column tiles of group b-2
+  // (bound by memory latency), so the two workgroups of a CU tend to hold
+  // tasks of both kinds.  Every prerequisite still precedes its dependants:
+  // the forward tiles of a group come in an earlier block than its rows, and
+  // its rows in an earlier block than its inverse tiles.
   std::vector<int> big;
   for (int p = 0; p < np; p++)
     if (prods[p].n > (uint32_t)kRowLog) big.push_back(p);
   std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return prods[x].n > prods[y].n; });
   std::stable_sort(small.begin(), small.end(), [&](uint2 x, uint2 y) { return prods[x.x].n > prods[y.x].n; });
+  double total = 0;
+  for (int p : big) total += std::ldexp(1.0, (int)prods[p].n) * prods[p].n;
+  const int ng = big.empty() ? 0 : kPipeGroups;
+  std::vector<std::vector<uint2>> colf_g(ng), row_g(ng), coli_g(ng);
+  double acc = 0;
   for (int p : big) {
     const ProdDev& pd = prods[p];
-    for (uint32_t t = 0; t < pd.ntiles; t++) colf.push_back(make_uint2((uint32_t)p, (T_COLF_A << 28) | t));
-    for (uint32_t t = 0; t < pd.ntiles; t++) colf.push_back(make_uint2((uint32_t)p, (T_COLF_B << 28) | t));
-    for (uint32_t j = 0; j < pd.nblocks; j++) row.push_back(make_uint2((uint32_t)p, (T_ROW << 28) | j));
-    for (uint32_t t = 0; t < pd.ntiles; t++) coli.push_back(make_uint2((uint32_t)p, (T_COLI << 28) | t));
+    const int g = std::min(ng - 1, (int)(acc / total * ng));
+    acc += std::ldexp(1.0, (int)pd.n) * pd.n;
+    for (uint32_t t = 0; t < pd.ntiles; t++) colf_g[g].push_back(make_uint2((uint32_t)p, (T_COLF_A << 28) | t));
+    for (uint32_t t = 0; t < pd.ntiles; t++) colf_g[g].push_back(make_uint2((uint32_t)p, (T_COLF_B << 28) | t));
+    for (uint32_t j = 0; j < pd.nblocks; j++) row_g[g].push_back(make_uint2((uint32_t)p, (T_ROW << 28) | j));
+    for (uint32_t t = 0; t < pd.ntiles; t++) coli_g[g].push_back(make_uint2((uint32_t)p, (T_COLI << 28) | t));
   }
+  // Single-task products are spread over the blocks.
+  const int nblk = ng + 2;
+  std::vector<std::vector<uint2>> small_b(nblk);
+  for (size_t i = 0; i < small.size(); i++) small_b[i * nblk / small.size()].push_back(small[i]);
   if (order_seed != 0) {
-    // Any order within a group keeps prerequisites earlier in the list.
+    // Any order within a list keeps prerequisites earlier in the whole list.
     std::mt19937_64 rng(order_seed);
-    std::shuffle(colf.begin(), colf.end(), rng);
-    std::shuffle(small.begin(), small.end(), rng);
-    std::shuffle(row.begin(), row.end(), rng);
-    std::shuffle(coli.begin(), coli.end(), rng);
+    for (int g = 0; g < ng; g++) {
+      std::shuffle(colf_g[g].begin(), colf_g[g].end(), rng);
+      std::shuffle(row_g[g].begin(), row_g[g].end(), rng);
+      std::shuffle(coli_g[g].begin(), coli_g[g].end(), rng);
+    }
+    for (auto& v : small_b) std::shuffle(v.begin(), v.end(), rng);
   }
-  tasks.reserve(colf.size() + small.size() + row.size() + coli.size());
-  size_t half = small.size() / 2;
-  tasks.insert(tasks.end(), colf.begin(), colf.end());
-  tasks.insert(tasks.end(), small.begin(), small.begin() + half);
-  tasks.insert(tasks.end(), row.begin(), row.end());
-  tasks.insert(tasks.end(), small.begin() + half, small.end());
-  tasks.insert(tasks.end(), coli.begin(), coli.end());
+  tasks.reserve(product_task_total(prods));
+  // Block b (0 .. ng+1) holds the forward tiles of group b, the rows of group
+  // b-1, the inverse tiles of group b-2 and a share of the single tasks,
+  // merged in proportion to their lengths.
+  for (int b = 0; b < nblk; b++) {
+    const std::vector<uint2>* parts[4] = {b < ng ? &colf_g[b] : nullptr,
+                                          b >= 1 && b - 1 < ng ? &row_g[b - 1] : nullptr,
+                                          b >= 2 && b - 2 < ng ? &coli_g[b - 2] : nullptr, &small_b[b]};
+    size_t pos[4] = {0, 0, 0, 0}, len[4];
+    size_t left = 0;
+    for (int i = 0; i < 4; i++) left += (len[i] = parts[i] ? parts[i]->size() : 0);
+    while (left > 0) {
+      int pick = -1;
+      double best = 2.0;
+      for (int i = 0; i < 4; i++) {
+        if (pos[i] >= len[i]) continue;
+        const double f = (pos[i] + 0.5) / (double)len[i];
+        if (f < best) best = f, pick = i;
+      }
+      tasks.push_back((*parts[pick])[pos[pick]++]);
+      left--;
+    }
+  }
   scr_words = scr;
   return MONT_OK;
 }
