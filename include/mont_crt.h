@@ -3,10 +3,10 @@
  * products modulo 31-bit Fourier primes (mont_ntt.h) joined by the Chinese
  * remainder theorem, on AMD Instinct MI355X (gfx950).
  *
- * The paper's modular arithmetic serves modular FFT libraries and large
- * integer and polynomial arithmetic (arXiv:1609.00999, sections 1 and 5);
- * products with coefficients wider than one word are what such libraries
- * build from several word-size primes.  For uint32 coefficients and
+ * The paper's word-size modular arithmetic serves computer algebra,
+ * polynomial arithmetic and modular FFT libraries (arXiv:1609.00999, sections
+ * 1 and 5); products whose coefficients outgrow one word are built from
+ * several word-size primes, the multi-modular route.  For uint32 coefficients and
  * min(da, db) + 1 <= 2^26, every coefficient of the integer product is below
  * 2^64 (min(da, db) + 1) <= 2^90 < P1 P2 P3, so the three residues determine
  * it.  The reconstruction is Garner's mixed-radix form
