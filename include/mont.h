@@ -118,6 +118,17 @@ MONT_API mont_status mont_pow(const mont_params* prm, const uint32_t* d_base, co
                      size_t n, void* stream);
 
 /*
+ * mont_modmul -- d_out[i] = d_a[i] * d_b[i] mod P for ORDINARY values (any
+ * uint32, not residues): the to / mul / from pipeline of section 3.1 in one
+ * pass, with two Montgomery products instead of four: REDC(d_b[i] * R2) is
+ * the residue of d_b[i], and REDC(d_a[i] * that) = d_a[i] d_b[i] mod P
+ * (the product stays below R P for every uint32 operand).  Canonical output;
+ * in place allowed.
+ */
+MONT_API mont_status mont_modmul(const mont_params* prm, const uint32_t* d_a, const uint32_t* d_b, uint32_t* d_out,
+                                 size_t n, void* stream);
+
+/*
  * mont_check_range -- checked mode of the operand contract above: if any
  * d_x[i] >= P for i < n, stores MONT_ERANGE into the device word *d_status;
  * otherwise it does not write *d_status at all.  A status word the caller has
@@ -203,7 +214,7 @@ MONT_API mont_status mont_batch_destroy(mont_batch* b);
 
 /*
  * Launch-shape tuning of the streaming elementwise kernels (used by the
- * autotuner).  op: 0 = to, 1 = from, 2 = mul, 3 = muladd, 4 = pow.  block is
+ * autotuner).  op: 0 = to, 1 = from, 2 = mul, 3 = muladd, 4 = pow, 5 = modmul.  block is
  * 64, 128, 256 or 512 threads, vpt 1, 2 or 4 128-bit vectors per thread, nontemporal
  * 0 or 1.  Settings are process-wide and take effect on the next call; they
  * never change results.  Returns MONT_EINVAL for values outside those sets.

@@ -89,6 +89,9 @@ __device__ __forceinline__ uint32_t elem_op(uint32_t a, uint32_t b, uint32_t c, 
   else if constexpr (OP == OP_MUL) return mmul(a, b, md);
   else if constexpr (OP == OP_MULADD) return madd(mmul(a, b, md), c, md.P);
   else if constexpr (OP == OP_POW_LAZY) return pow_win2_lazy(a, b, md, kc);
+  // a b mod P of ordinary values: REDC(b R2) = b R mod P, then
+  // REDC(a * bR) = a b; a * bR < 2^32 P = R P for every uint32 a, b.
+  else if constexpr (OP == OP_MODMUL) return mmul(a, mmul(b, kc, md), md);   // kc = R^2 mod P
   else return pow_win2(a, b, md, kc);                             // kc = residue of 1
 }
 
@@ -214,7 +217,7 @@ void dispatch(const ElemTune& t, Mod md, uint32_t kc, const uint32_t* a, const u
 }
 
 ElemTune g_tune[OP_COUNT] = {
-    {256, 1, 1}, {256, 1, 1}, {256, 1, 1}, {256, 1, 1}, {256, 1, 1},
+    {256, 1, 1}, {256, 1, 1}, {256, 1, 1}, {256, 1, 1}, {256, 1, 1}, {64, 1, 1},
 };
 
 mont_status run(int op, const mont_params* prm, const uint32_t* a, const uint32_t* b, const uint32_t* c,
@@ -222,7 +225,7 @@ mont_status run(int op, const mont_params* prm, const uint32_t* a, const uint32_
   if (!params_ok(prm)) return MONT_EINVAL;
   if (n == 0) return MONT_OK;
   if (!a || !out) return MONT_EINVAL;
-  if ((op == OP_MUL || op == OP_MULADD || op == OP_POW) && !b) return MONT_EINVAL;
+  if ((op == OP_MUL || op == OP_MULADD || op == OP_POW || op == OP_MODMUL) && !b) return MONT_EINVAL;
   if (op == OP_MULADD && !c) return MONT_EINVAL;
   Mod md{prm->P, prm->Pprime};
   hipStream_t s = as_stream(stream);
@@ -233,6 +236,7 @@ mont_status run(int op, const mont_params* prm, const uint32_t* a, const uint32_
     case OP_FROM: dispatch<OP_FROM>(t, md, 0, a, nullptr, nullptr, out, n, s); break;
     case OP_MUL: dispatch<OP_MUL>(t, md, 0, a, b, nullptr, out, n, s); break;
     case OP_MULADD: dispatch<OP_MULADD>(t, md, 0, a, b, c, out, n, s); break;
+    case OP_MODMUL: dispatch<OP_MODMUL>(t, md, prm->R2, a, b, nullptr, out, n, s); break;
     default:
       if (prm->P < (1u << 30)) dispatch<OP_POW_LAZY>(t, md, prm->R1, a, b, nullptr, out, n, s);
       else dispatch<OP_POW>(t, md, prm->R1, a, b, nullptr, out, n, s);
@@ -272,4 +276,9 @@ extern "C" mont_status mont_muladd(const mont_params* prm, const uint32_t* d_a, 
 extern "C" mont_status mont_pow(const mont_params* prm, const uint32_t* d_base, const uint32_t* d_exp,
                                 uint32_t* d_out, size_t n, void* stream) {
   return run(OP_POW, prm, d_base, d_exp, nullptr, d_out, n, stream);
+}
+
+extern "C" mont_status mont_modmul(const mont_params* prm, const uint32_t* d_a, const uint32_t* d_b,
+                                   uint32_t* d_out, size_t n, void* stream) {
+  return run(OP_MODMUL, prm, d_a, d_b, nullptr, d_out, n, stream);
 }

@@ -36,7 +36,7 @@ struct ElemTune {
   int nt;     // 1 = non-temporal loads and stores
 };
 
-enum ElemOp { OP_TO = 0, OP_FROM = 1, OP_MUL = 2, OP_MULADD = 3, OP_POW = 4, OP_COUNT = 5 };
+enum ElemOp { OP_TO = 0, OP_FROM = 1, OP_MUL = 2, OP_MULADD = 3, OP_POW = 4, OP_MODMUL = 5, OP_COUNT = 6 };
 
 ElemTune& elem_tune(int op);
 

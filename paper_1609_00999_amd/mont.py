@@ -57,7 +57,7 @@ def lib() -> ctypes.CDLL:
     for name in ("mont_mul", "mont_pow"):
         getattr(L, name).argtypes = [pp, c_vp, c_vp, c_vp, c_size, c_vp]
     L.mont_muladd.argtypes = [pp, c_vp, c_vp, c_vp, c_vp, c_size, c_vp]
-    for name in ("mont_mul_fourier", "mont_pow_fourier"):
+    for name in ("mont_mul_fourier", "mont_pow_fourier", "mont_modmul"):
         getattr(L, name).argtypes = [pp, c_vp, c_vp, c_vp, c_size, c_vp]
     for name in ("modmul_barrett", "modpow_barrett"):
         getattr(L, name).argtypes = [c_u32, c_vp, c_vp, c_vp, c_size, c_vp]
@@ -292,6 +292,20 @@ def _binary(fn, first, a, b, out, name, P, check_b):
     return out
 
 
+def modmul(prm: MontParams, a, b, out=None):
+    """a*b mod P of ORDINARY uint32 values in one pass (mont_modmul); no
+    conversion to residues needed, any uint32 operand accepted."""
+    if a.numel() != b.numel():
+        raise ValueError("operand sizes differ")
+    if out is None:
+        out = empty_like_u32(a)
+    if out.numel() != a.numel():
+        raise ValueError("out size differs")
+    check(lib().mont_modmul(ctypes.byref(prm), dev_ptr(a, "a"), dev_ptr(b, "b"), dev_ptr(out, "out"), a.numel(),
+                            stream_handle()), "mont_modmul")
+    return out
+
+
 def mul_fourier(prm: MontParams, a, b, out=None):
     """Algorithm 3 (Fourier-prime REDC) elementwise; same result as mul()."""
     return _binary(lib().mont_mul_fourier, ctypes.byref(prm), a, b, out, "mont_mul_fourier", prm.P, True)
@@ -356,7 +370,7 @@ class Batch:
         check(lib().mont_batch_mul(self.handle, stream_handle()), "mont_batch_mul")
 
 
-ELEM_OPS = {"to": 0, "from": 1, "mul": 2, "muladd": 3, "pow": 4}
+ELEM_OPS = {"to": 0, "from": 1, "mul": 2, "muladd": 3, "pow": 4, "modmul": 5}
 
 
 def elem_tune_set(op: str, block: int, vpt: int, nontemporal: bool) -> None:

@@ -82,7 +82,7 @@ def apply(cache: dict, arch: str, lib) -> dict:
     """Set the tuned launch shapes of `arch` through the C ABI; returns what
     was applied."""
     applied = {}
-    for op, idx in (("to", 0), ("from", 1), ("mul", 2), ("muladd", 3), ("pow", 4)):
+    for op, idx in (("to", 0), ("from", 1), ("mul", 2), ("muladd", 3), ("pow", 4), ("modmul", 5)):
         cfg = choose(cache, arch, "elem_" + op)
         if cfg and lib.mont_elem_tune_set(idx, int(cfg[0]), int(cfg[1]), int(cfg[2])) == 0:
             applied["elem_" + op] = cfg
@@ -114,7 +114,7 @@ def _time(torch, fn, reps):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-def tune_elementwise(n_log2: int = 28, reps: int = 5, ops=("to", "from", "mul", "muladd", "pow")):
+def tune_elementwise(n_log2: int = 28, reps: int = 5, ops=("to", "from", "mul", "muladd", "pow", "modmul")):
     import torch
     from . import mont
     n = 1 << n_log2
@@ -127,7 +127,8 @@ def tune_elementwise(n_log2: int = 28, reps: int = 5, ops=("to", "from", "mul", 
     o = torch.empty_like(a)
     calls = {"to": lambda: mont.to_mont(prm, a, out=o), "from": lambda: mont.from_mont(prm, a, out=o),
              "mul": lambda: mont.mul(prm, a, b, out=o), "muladd": lambda: mont.muladd(prm, a, b, c, out=o),
-             "pow": lambda: mont.pow(prm, a, b, out=o)}
+             "pow": lambda: mont.pow(prm, a, b, out=o),
+             "modmul": lambda: mont.modmul(prm, a, b, out=o)}
     out = {}
     for op in ops:
         old = mont.elem_tune_get(op)

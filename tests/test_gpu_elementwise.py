@@ -290,3 +290,36 @@ def test_pow_both_reduction_paths(M, P):
     ex[: 8 * e.size] = np.tile(np.array([0, 1, 2, 3, 0xFFFFFFFF, 0xAAAAAAAA, 0x55555555, P - 1], dtype=np.uint64)
                                .astype(np.uint32), e.size)
     assert np.array_equal(host(M.pow(prm, dev(base), dev(ex))), oracle.mont_pow(P, base, ex))
+
+
+@pytest.mark.parametrize("P", MODULI)
+def test_fused_modmul_ordinary_values(M, P):
+    """mont_modmul: a*b mod P of ordinary uint32 values (not reduced, not
+    residues) in one pass, against the plain product."""
+    prm = M.setup(P)
+    rng = np.random.default_rng(P % 8191)
+    x = rng.integers(0, 1 << 32, 60001, dtype=np.uint64).astype(np.uint32)
+    y = rng.integers(0, 1 << 32, 60001, dtype=np.uint64).astype(np.uint32)
+    ed = np.array([0, 1, P - 1, P, P + 1, 0xFFFFFFFF, 1 << 31, (1 << 31) - 1], dtype=np.uint64).astype(np.uint32)
+    x = np.concatenate([np.repeat(ed, ed.size), x])
+    y = np.concatenate([np.tile(ed, ed.size), y])
+    want = oracle.modmul(P, x, y)
+    assert np.array_equal(host(M.modmul(prm, dev(x), dev(y))), want)
+    for off, n in ((1, 1), (1, 1001), (3, 4099), (0, 7)):           # misaligned views and ragged tails
+        assert np.array_equal(host(M.modmul(prm, dev(x)[off:off + n], dev(y)[off:off + n])), want[off:off + n])
+    dx = dev(x)
+    M.modmul(prm, dx, dev(y), out=dx)                             # in place
+    assert np.array_equal(host(dx), want)
+
+
+def test_fused_modmul_pipeline_config(M):
+    """The plain pipeline config (2^20 pairs, P = 15*2^27+1) through the fused
+    call equals the to / mul / from path and the plain product."""
+    P = wl.P_PLAIN
+    prm = M.setup(P)
+    a, b = wl.plain_pairs()
+    da, db = dev(a), dev(b)
+    fused = host(M.modmul(prm, da, db))
+    staged = host(M.from_mont(prm, M.mul(prm, M.to_mont(prm, da), M.to_mont(prm, db))))
+    assert np.array_equal(fused, staged)
+    assert np.array_equal(fused, ((a.astype(np.uint64) * b) % P).astype(np.uint32))
