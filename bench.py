@@ -197,7 +197,7 @@ def main():
         result["cpu_baseline"] = cpu_baseline(host_sets)
 
     if not args.no_extras:
-        result["extras"] = extras(torch, mont, wl, dev)
+        result["extras"] = extras(torch, mont, wl, dev, cpu=not args.no_cpu_baseline)
 
     print(json.dumps(result), flush=True)
 
@@ -224,6 +224,33 @@ def cpu_baseline(host_sets):
             "sample": "%d full steps (mont_mul and mont_muladd over 2^28 elements for each of the 4 primes), "
                       "repeated until at least 10 s of host time" % reps,
             "seconds": round(dt, 2), "cpu_model": cpu_model()}
+
+
+def cpu_pow_sample(wl, n=1 << 22):
+    """The oracle's powers on the first n bases of the 2^24 power workload,
+    all host threads."""
+    import oracle
+    base, e = wl.pow_inputs()
+    t0 = time.perf_counter()
+    oracle.mont_pow(wl.P_POW, base[:n], e[:n])
+    dt = time.perf_counter() - t0
+    return {"pow_per_s": round(n / dt, 1), "sample": "first %d of the 2^24 bases" % n,
+            "seconds": round(dt, 2), "cores": oracle.default_threads(), "kind": "oracle"}
+
+
+def cpu_polymul_sample(wl, count=96):
+    """The oracle's products (its plain transform, host threads) on every
+    21st product of the 2048-product batch, scaled to products per second of
+    the same size mix."""
+    import oracle
+    batch = wl.polymul_batch()
+    idx = list(range(0, batch.count, batch.count // count))[:count]
+    t0 = time.perf_counter()
+    oracle.polymul_many([batch.operands(i) for i in idx])
+    dt = time.perf_counter() - t0
+    return {"polymul_per_s": round(len(idx) / dt, 1), "sample": "%d of the 2048 products (one in %d)"
+            % (len(idx), batch.count // count), "seconds": round(dt, 2), "cores": oracle.default_threads(),
+            "kind": "oracle"}
 
 
 def cpu_model():
@@ -253,8 +280,9 @@ def timed(torch, fn, reps=5):
 EXTRAS = ("pipeline", "pow", "reductions", "mont64", "crt", "polymul", "serving")
 
 
-def extras(torch, mont, wl, dev, which=EXTRAS):
-    """Side measurements of the other rows, by name (EXTRAS)."""
+def extras(torch, mont, wl, dev, which=EXTRAS, cpu=False):
+    """Side measurements of the other rows, by name (EXTRAS); with cpu=True
+    the power and batch rows also time the oracle on a bounded sample."""
     out = {}
     if "pipeline" in which:
         out["plain_pipeline_n2^20"] = pipeline_extra(torch, mont, wl, dev)
@@ -270,6 +298,10 @@ def extras(torch, mont, wl, dev, which=EXTRAS):
         out["crt_int_products_256"] = crt_extra(torch, wl, dev)
     if "polymul" in which:
         out["polymul_batch_2048"] = polymul_batch_extra(torch, wl, dev)
+    if cpu and "pow" in which:
+        out.setdefault("pow_n2^24", {})["cpu_oracle"] = cpu_pow_sample(wl)
+    if cpu and "polymul" in which:
+        out["polymul_batch_2048"]["cpu_oracle"] = cpu_polymul_sample(wl)
     if "serving" in which:
         out["serving"] = serving_extra(torch, wl, dev)
     return out
