@@ -226,8 +226,8 @@ def cpu_baseline(host_sets):
             "seconds": round(dt, 2), "cpu_model": cpu_model()}
 
 
-def cpu_pow_sample(wl, n=1 << 22):
-    """The oracle's powers on the first n bases of the 2^24 power workload,
+def cpu_pow_sample(wl, n=1 << 24):
+    """The oracle's powers on the 2^24 bases of the power workload (n of them),
     all host threads."""
     import oracle
     base, e = wl.pow_inputs()
