@@ -277,7 +277,7 @@ def timed(torch, fn, reps=5):
     return e0.elapsed_time(e1) / reps / 1e3
 
 
-EXTRAS = ("pipeline", "pow", "reductions", "mont64", "crt", "polymul", "serving")
+EXTRAS = ("pipeline", "pow", "reductions", "vectors", "mont64", "crt", "polymul", "serving")
 
 
 def extras(torch, mont, wl, dev, which=EXTRAS, cpu=False):
@@ -292,6 +292,8 @@ def extras(torch, mont, wl, dev, which=EXTRAS, cpu=False):
             out["pow_n2^24"] = pw
         if red is not None:
             out["reductions_P998244353"] = red
+    if "vectors" in which:
+        out["vector_batch_4096"] = vector_batch_extra(torch, mont, wl, dev)
     if "mont64" in which:
         out["mont64"] = mont64_extra(torch, wl, dev)
     if "crt" in which:
@@ -368,6 +370,56 @@ def pow_extras(torch, mont, wl, dev, reductions):
         red[name]["mul_n2^28_us"] = round(s * 1e6, 1)
         red[name]["mul_GB_per_s"] = round(12 * n / s / 1e9, 1)
     return pw, red
+
+
+def vector_batch_extra(torch, mont, wl, dev):
+    """4096 elementwise products of uneven lengths (n log-uniform in
+    [2^10, 2^20)), each with its own prime: one mont_batch_mul launch against
+    one mont_mul launch per vector, on the same resident operands."""
+    import oracle
+    sizes, pid = wl.vector_batch()
+    primes = wl.PRIMES_NTT
+    params = [mont.setup(P) for P in primes]
+    g = torch.Generator(device=dev)
+    g.manual_seed(wl.SEED_VEC)
+    total = int(sizes.sum())
+    # one arena per role, every vector 16-byte aligned
+    offs = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum((sizes + 3) // 4 * 4)
+    A = torch.empty(int(offs[-1]), dtype=torch.int32, device=dev)
+    B = torch.empty_like(A)
+    O1 = torch.empty_like(A)
+    O2 = torch.empty_like(A)
+    for i, (n, p) in enumerate(zip(sizes.tolist(), pid.tolist())):
+        o = int(offs[i])
+        A[o:o + n] = torch.randint(0, primes[p], (n,), dtype=torch.int32, device=dev, generator=g)
+        B[o:o + n] = torch.randint(0, primes[p], (n,), dtype=torch.int32, device=dev, generator=g)
+    items = [(params[p], A[int(offs[i]):int(offs[i]) + n], B[int(offs[i]):int(offs[i]) + n],
+              O1[int(offs[i]):int(offs[i]) + n]) for i, (n, p) in enumerate(zip(sizes.tolist(), pid.tolist()))]
+    batch = mont.Batch(len(items))
+    batch.update(items)
+    t_batch = timed(torch, batch.mul, 10)
+
+    def plain():
+        for (prm, a, b, _), i in zip(items, range(len(items))):
+            o = int(offs[i])
+            mont.mul(prm, a, b, out=O2[o:o + a.numel()])
+    t_plain = timed(torch, plain, 3)
+    # spot check: the batch equals the per-vector launches, and three vectors the oracle
+    same = bool(torch.equal(O1, O2))
+    bad = 0
+    for i in (0, len(items) // 2, len(items) - 1):
+        prm, a, b, o = items[i]
+        bad += not np.array_equal(o.cpu().numpy().view(np.uint32),
+                                  oracle.mont_mul(prm.P, a.cpu().numpy().view(np.uint32),
+                                                  b.cpu().numpy().view(np.uint32)))
+    batch.close()
+    byts = 12.0 * total
+    return {"vectors": len(items), "elements": total, "batch_us": round(t_batch * 1e6, 1),
+            "batch_GB_per_s": round(byts / t_batch / 1e9, 1), "batch_frac_of_peak": round(byts / t_batch / 1e9 /
+                                                                                      HBM_PEAK_GBS, 4),
+            "plain_launches_us": round(t_plain * 1e6, 1), "speedup_vs_plain": round(t_plain / t_batch, 2),
+            "batch_equals_plain": same, "spot_check_failures": int(bad)}
 
 
 def mont64_extra(torch, wl, dev):

@@ -35,12 +35,15 @@ struct VecDev {
   uint32_t P, Pp;
 };
 
-__global__ __launch_bounds__(kBatchThreads) void k_batch_mul(const VecDev* vecs, uint32_t nvec, uint64_t ntiles) {
+// tile_begin[v] repeats vecs[v].tile_begin in a contiguous array, so the
+// binary search touches a few cache lines instead of one descriptor each.
+__global__ __launch_bounds__(kBatchThreads) void k_batch_mul(const VecDev* vecs, const uint64_t* tile_begin,
+                                                             uint32_t nvec, uint64_t ntiles) {
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     uint32_t lo = 0, hi = nvec - 1;             // last v with tile_begin[v] <= t
     while (lo < hi) {
       const uint32_t mid = (lo + hi + 1) >> 1;
-      if (vecs[mid].tile_begin <= t) lo = mid;
+      if (tile_begin[mid] <= t) lo = mid;
       else hi = mid - 1;
     }
     const VecDev v = vecs[lo];
@@ -85,6 +88,8 @@ struct mont_batch {
   uint64_t ntiles = 0;
   VecDev* d_vecs = nullptr;
   VecDev* h_vecs = nullptr;       // pinned staging
+  uint64_t* d_begin = nullptr;    // tile_begin of every vector, contiguous
+  uint64_t* h_begin = nullptr;
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   int grid = 0;
@@ -94,7 +99,9 @@ namespace {
 
 void free_batch(mont_batch* b) {
   (void)hipFree(b->d_vecs);
+  (void)hipFree(b->d_begin);
   if (b->h_vecs) (void)hipHostFree(b->h_vecs);
+  if (b->h_begin) (void)hipHostFree(b->h_begin);
   if (b->staged) (void)hipEventDestroy(b->staged);
   delete b;
 }
@@ -108,15 +115,16 @@ extern "C" mont_status mont_batch_reserve(int max_vectors, mont_batch** out) {
   if (!b) return MONT_ENOMEM;
   b->cap = max_vectors;
   if (hipMalloc(&b->d_vecs, sizeof(VecDev) * max_vectors) != hipSuccess ||
+      hipMalloc(&b->d_begin, sizeof(uint64_t) * max_vectors) != hipSuccess ||
       hipHostMalloc((void**)&b->h_vecs, sizeof(VecDev) * max_vectors, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->h_begin, sizeof(uint64_t) * max_vectors, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
     free_batch(b);
     return MONT_ENOMEM;
   }
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  b->grid = cus * 8;
+  // One workgroup per tile (the launch shape that streams best), striding
+  // over tiles only beyond 2^20 of them.
+  b->grid = 1 << 20;
   *out = b;
   return MONT_OK;
 }
@@ -141,6 +149,7 @@ extern "C" mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* des
     v.out = d.out;
     v.n = d.n;
     v.tile_begin = tiles;
+    b->h_begin[i] = tiles;
     v.P = d.P;
     v.Pp = d.Pprime;
     tiles += (d.n + kBatchTile - 1) / kBatchTile;
@@ -150,6 +159,7 @@ extern "C" mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* des
   if (count > 0) {
     hipStream_t s = as_stream(stream);
     if (hipMemcpyAsync(b->d_vecs, b->h_vecs, sizeof(VecDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(b->d_begin, b->h_begin, sizeof(uint64_t) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipEventRecord(b->staged, s) != hipSuccess)
       return MONT_EHIP;
     b->staged_pending = true;
@@ -163,7 +173,7 @@ extern "C" mont_status mont_batch_mul(const mont_batch* b, void* stream) {
   (void)hipGetLastError();
   uint64_t grid = b->ntiles < (uint64_t)b->grid ? b->ntiles : (uint64_t)b->grid;
   hipLaunchKernelGGL(k_batch_mul, dim3((unsigned)grid), dim3(kBatchThreads), 0, as_stream(stream), b->d_vecs,
-                     (uint32_t)b->count, b->ntiles);
+                     b->d_begin, (uint32_t)b->count, b->ntiles);
   return last_launch_status();
 }
 

@@ -33,6 +33,7 @@ SEED_SERVE = 5
 SEED_BW64_BASE = 600
 SEED_POW64 = 7
 SEED_CRT = 8
+SEED_VEC = 9
 
 
 def uniform(rng: np.random.Generator, lo: int, hi: int, n: int) -> np.ndarray:
@@ -198,3 +199,14 @@ def int_products(count: int = 256, lo_log2: float = 8, hi_log2: float = 18, seed
     rng = np.random.default_rng(seed)
     d = log_uniform(rng, lo_log2, hi_log2, count)
     return pack_products((1 << 32,), np.zeros(count, dtype=np.int64), d, d, rng)
+
+
+def vector_batch(count: int = 4096, lo_log2: float = 10, hi_log2: float = 20, seed: int = SEED_VEC,
+                 primes=PRIMES_NTT):
+    """Sizes and primes of a batch of uneven elementwise products: n =
+    floor(2^U), U ~ U[lo, hi), each vector with a prime drawn uniformly.
+    (Operand values are drawn on the device by the caller.)"""
+    rng = np.random.default_rng(seed)
+    n = log_uniform(rng, lo_log2, hi_log2, count)
+    prime_id = rng.integers(0, len(primes), size=count)
+    return n, prime_id
