@@ -24,7 +24,8 @@ __device__ __forceinline__ bool aligned16_dev(const void* p) { return ((uintptr_
 // ---------------------------------------------------------------------------
 
 constexpr int kBatchThreads = 256;
-constexpr uint32_t kBatchTile = 4096;   // residues per tile: 4 per lane, 4 rounds
+constexpr int kBatchVpt = 4;            // 128-bit vectors per lane per tile
+constexpr uint32_t kBatchTile = 4u * kBatchThreads * kBatchVpt;   // residues per tile
 
 struct VecDev {
   const uint32_t* a;
@@ -55,14 +56,14 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_mul(const VecDev* vecs,
       const v4u* va = reinterpret_cast<const v4u*>(v.a + e0);
       const v4u* vb = reinterpret_cast<const v4u*>(v.b + e0);
       v4u* vo = reinterpret_cast<v4u*>(v.out + e0);
-      v4u x[4], y[4];
+      v4u x[kBatchVpt], y[kBatchVpt];
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
+      for (int j = 0; j < kBatchVpt; j++) {
         x[j] = __builtin_nontemporal_load(va + j * kBatchThreads + threadIdx.x);
         y[j] = __builtin_nontemporal_load(vb + j * kBatchThreads + threadIdx.x);
       }
 #pragma unroll
-      for (int j = 0; j < 4; j++) {
+      for (int j = 0; j < kBatchVpt; j++) {
         v4u r;
         r.x = mmul(x[j].x, y[j].x, md);
         r.y = mmul(x[j].y, y[j].y, md);
