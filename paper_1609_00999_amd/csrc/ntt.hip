@@ -134,6 +134,62 @@ __device__ __forceinline__ uint32_t ldg(const uint32_t* p, uint32_t i) {
   return ((gptr_u32)p)[i];
 }
 
+// Stores whose data another workgroup reads later in the same persistent
+// launch are agent-scope atomic stores (global_store ... sc1): they are
+// written through to the device coherence point, so a consumer on another
+// XCD sees them once they have completed, and no L2 write-back is needed
+// when the task is published.
+template <bool COH>
+__device__ __forceinline__ void st_out(uint32_t* p, uint32_t v) {
+  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
+// Lower output of the forward (decimation-in-frequency) butterfly,
+// (x - y) w mod P for x, y in [0, P) and w a twiddle in Montgomery form.
+// With wn = P - w, x w + y wn = (x - y) w mod P and the sum is below P^2 < R P,
+// Algorithm 2's precondition, so REDC takes it directly: two v_mad_u64_u32
+// replace the subtraction, the add of P and the product.
+__device__ __forceinline__ uint32_t bfly_lo(uint32_t x, uint32_t y, uint32_t w, uint32_t wn, Mod md) {
+  return redc((uint64_t)x * w + (uint64_t)y * wn, md);
+}
+
+// The R radix-2 stages of one register round on a group of 2^R residues.
+// Stage t pairs elements 2^t apart; its twiddle for pair (j, j + 2^t) is
+// w[2^t - 1 + (j mod 2^t)] (wn holds P - w for the forward butterfly).
+template <int R>
+__device__ __forceinline__ void dif_stages(uint32_t* v, const uint32_t* w, const uint32_t* wn, Mod md) {
+  constexpr int E = 1 << R;
+#pragma unroll
+  for (int t = R - 1; t >= 0; t--) {
+    const int d = 1 << t;
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+      if (j & d) continue;
+      const uint32_t x = v[j], y = v[j + d];
+      v[j] = madd(x, y, md.P);
+      v[j + d] = bfly_lo(x, y, w[d - 1 + (j & (d - 1))], wn[d - 1 + (j & (d - 1))], md);
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void dit_stages(uint32_t* v, const uint32_t* w, Mod md) {
+  constexpr int E = 1 << R;
+#pragma unroll
+  for (int t = 0; t < R; t++) {
+    const int d = 1 << t;
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+      if (j & d) continue;
+      const uint32_t x = v[j];
+      const uint32_t y = mmul(v[j + d], w[d - 1 + (j & (d - 1))], md);
+      v[j] = madd(x, y, md.P);
+      v[j + d] = msub(x, y, md.P);
+    }
+  }
+}
+
 template <int NT, int NA, int R, bool INV>
 __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int s_lo, int lc, int rs,
                                           uint32_t colbase, const uint32_t* tw, Mod md) {
@@ -152,39 +208,19 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
 #pragma unroll
       for (int jj = 0; jj < (1 << t); jj++)
         w[(1 << t) - 1 + jj] = ldg(tw, (1u << (s_lo + t + rs)) + t0 + ((uint32_t)jj << (s_lo + rs)));
+    uint32_t wn[E - 1];
+    if constexpr (!INV) {
+#pragma unroll
+      for (int k = 0; k < E - 1; k++) wn[k] = md.P - w[k];
+    }
 #pragma nounroll
     for (int a = 0; a < NA; a++) {
       const uint32_t pb = lds_at((uint32_t)(a * off) + base);
       uint32_t v[E];
 #pragma unroll
       for (int j = 0; j < E; j++) v[j] = X[pb ^ lds_at((uint32_t)j << a_lo)];
-      if constexpr (!INV) {
-#pragma unroll
-        for (int t = R - 1; t >= 0; t--) {
-          const int d = 1 << t;
-#pragma unroll
-          for (int j = 0; j < E; j++) {
-            if (j & d) continue;
-            const uint32_t x = v[j], y = v[j + d];
-            v[j] = madd(x, y, md.P);
-            // x - y + P is in [1, 2P): REDC takes it as is ((2P) P < R P)
-            v[j + d] = mmul(x - y + md.P, w[d - 1 + (j & (d - 1))], md);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < R; t++) {
-          const int d = 1 << t;
-#pragma unroll
-          for (int j = 0; j < E; j++) {
-            if (j & d) continue;
-            const uint32_t x = v[j];
-            const uint32_t y = mmul(v[j + d], w[d - 1 + (j & (d - 1))], md);
-            v[j] = madd(x, y, md.P);
-            v[j + d] = msub(x, y, md.P);
-          }
-        }
-      }
+      if constexpr (!INV) dif_stages<R>(v, w, wn, md);
+      else dit_stages<R>(v, w, md);
 #pragma unroll
       for (int j = 0; j < E; j++) X[pb ^ lds_at((uint32_t)j << a_lo)] = v[j];
     }
@@ -320,6 +356,11 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
 #pragma unroll
       for (int jj = 0; jj < (1 << t); jj++)
         w[(1 << t) - 1 + jj] = ldg(twg, (1u << (S_LO + t + RS)) + ((uint32_t)jj << (S_LO + RS)));
+    uint32_t wn[E - 1];
+    if constexpr (!INV) {
+#pragma unroll
+      for (int k = 0; k < E - 1; k++) wn[k] = md.P - w[k];
+    }
 #pragma nounroll
     for (int a = 0; a < NA; a++) {
       const uint32_t yb = (uint32_t)(a * off) + base;
@@ -329,32 +370,8 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
       fill_group_addr<A_LO, R, 0>(ad, yb, pb);
 #pragma unroll
       for (int j = 0; j < E; j++) v[j] = X[ad[j]];
-      if constexpr (!INV) {
-#pragma unroll
-        for (int t = R - 1; t >= 0; t--) {
-          const int d = 1 << t;
-#pragma unroll
-          for (int j = 0; j < E; j++) {
-            if (j & d) continue;
-            const uint32_t x = v[j], y = v[j + d];
-            v[j] = madd(x, y, md.P);
-            v[j + d] = mmul(x - y + md.P, w[d - 1 + (j & (d - 1))], md);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < R; t++) {
-          const int d = 1 << t;
-#pragma unroll
-          for (int j = 0; j < E; j++) {
-            if (j & d) continue;
-            const uint32_t x = v[j];
-            const uint32_t y = mmul(v[j + d], w[d - 1 + (j & (d - 1))], md);
-            v[j] = madd(x, y, md.P);
-            v[j + d] = msub(x, y, md.P);
-          }
-        }
-      }
+      if constexpr (!INV) dif_stages<R>(v, w, wn, md);
+      else dit_stages<R>(v, w, md);
 #pragma unroll
       for (int j = 0; j < E; j++) X[ad[j]] = v[j];
     }
@@ -362,22 +379,126 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
   __syncthreads();
 }
 
-template <int NT, int NA, int RM, int LR, int LC, int RS, int IDX = 0>
+// Forward rounds IDX .. END-1 (all of them by default).
+template <int NT, int NA, int RM, int LR, int LC, int RS, int IDX = 0, int END = fixed_nrounds<LR, RM>()>
 __device__ __forceinline__ void fixed_dif(uint32_t* X, int off, uint32_t colbase, const uint32_t* tw, Mod md) {
-  if constexpr (IDX < fixed_nrounds<LR, RM>()) {
+  if constexpr (IDX < END) {
     lds_round_fixed<NT, NA, fixed_rsize<LR, RM>(IDX), false, LR, LC, RS, fixed_dif_slo<LR, RM>(IDX)>(X, off, colbase,
                                                                                                      tw, md);
-    fixed_dif<NT, NA, RM, LR, LC, RS, IDX + 1>(X, off, colbase, tw, md);
+    fixed_dif<NT, NA, RM, LR, LC, RS, IDX + 1, END>(X, off, colbase, tw, md);
   }
 }
 
-template <int NT, int RM, int LR, int LC, int RS, int IDX = 0>
+// Inverse rounds IDX .. END-1 (all of them by default).
+template <int NT, int RM, int LR, int LC, int RS, int IDX = 0, int END = fixed_nrounds<LR, RM>()>
 __device__ __forceinline__ void fixed_dit(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
-  if constexpr (IDX < fixed_nrounds<LR, RM>()) {
+  if constexpr (IDX < END) {
     lds_round_fixed<NT, 1, fixed_dit_rsize<LR, RM>(IDX), true, LR, LC, RS, fixed_dit_slo<LR, RM>(IDX)>(X, 0, colbase,
                                                                                                        tw, md);
-    fixed_dit<NT, RM, LR, LC, RS, IDX + 1>(X, colbase, tw, md);
+    fixed_dit<NT, RM, LR, LC, RS, IDX + 1, END>(X, colbase, tw, md);
   }
+}
+
+// The first forward round of a row-block product reads both blocks straight
+// from global memory and the last inverse round writes the product straight
+// back, instead of staging the blocks through LDS.  Both rounds cover the top
+// stages (first stage S_LO >= 9), where a group's residues lie 2^S_LO apart:
+// lane g of a wave takes group base g, so each of the 2^R loads or stores of
+// a wave covers 64 adjacent words, and the LDS address of element j is
+// lds_at(base) + j 2^S_LO (the swizzle leaves bits >= 9 alone).
+template <int NT, int R, int S_LO>
+__device__ __forceinline__ void row_round_in(uint32_t* X, uint32_t L, const uint32_t* gA, const uint32_t* gB,
+                                             const uint32_t* tw, Mod md) {
+  static_assert(S_LO >= 9, "the group stride must be above the swizzled bits");
+  constexpr int E = 1 << R;
+  constexpr uint32_t lomask = (1u << S_LO) - 1;
+  for (uint32_t g = threadIdx.x; g < ((1u << kRowLog) >> R); g += NT) {
+    const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
+    const uint32_t* twg = tw + (base & lomask);
+    uint32_t w[E - 1], wn[E - 1];
+#pragma unroll
+    for (int t = 0; t < R; t++)
+#pragma unroll
+      for (int jj = 0; jj < (1 << t); jj++) w[(1 << t) - 1 + jj] = ldg(twg, (1u << (S_LO + t)) + ((uint32_t)jj << S_LO));
+#pragma unroll
+    for (int k = 0; k < E - 1; k++) wn[k] = md.P - w[k];
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      const uint32_t* src = (a == 0 ? gA : gB) + base;
+      uint32_t v[E];
+#pragma unroll
+      for (int j = 0; j < E; j++) v[j] = src[(uint32_t)j << S_LO];
+      dif_stages<R>(v, w, wn, md);
+      const uint32_t pb = lds_at((uint32_t)a * L + base);
+#pragma unroll
+      for (int j = 0; j < E; j++) X[pb + ((uint32_t)j << S_LO)] = v[j];
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT, int R, int S_LO, bool COH>
+__device__ __forceinline__ void row_round_out(const uint32_t* X, uint32_t* gA, const uint32_t* tw, Mod md) {
+  static_assert(S_LO >= 9, "the group stride must be above the swizzled bits");
+  constexpr int E = 1 << R;
+  constexpr uint32_t lomask = (1u << S_LO) - 1;
+  for (uint32_t g = threadIdx.x; g < ((1u << kRowLog) >> R); g += NT) {
+    const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
+    const uint32_t* twg = tw + (base & lomask);
+    uint32_t w[E - 1];
+#pragma unroll
+    for (int t = 0; t < R; t++)
+#pragma unroll
+      for (int jj = 0; jj < (1 << t); jj++) w[(1 << t) - 1 + jj] = ldg(twg, (1u << (S_LO + t)) + ((uint32_t)jj << S_LO));
+    const uint32_t pb = lds_at(base);
+    uint32_t v[E];
+#pragma unroll
+    for (int j = 0; j < E; j++) v[j] = X[pb + ((uint32_t)j << S_LO)];
+    dit_stages<R>(v, w, md);
+#pragma unroll
+    for (int j = 0; j < E; j++) st_out<COH>(gA + base + ((uint32_t)j << S_LO), v[j]);
+  }
+}
+
+// The middle of a row-block product: the last forward round of both blocks,
+// their pointwise product and the first inverse round.  The forward's last
+// round and the inverse's first cover the same stages 0 .. R-1 on the same
+// groups of 2^R adjacent residues, and for those stages the twiddles are the
+// same for every group, so the three steps run on registers: LDS is read and
+// written once for them instead of three times, and two barriers go away.
+// A (L words) is at X[lds_at(0 ..)], B at X[lds_at(L ..)]; the product
+// replaces A.  A group lies inside one 64-word LDS row (R <= 6), where the
+// swizzle is the same for all its words.
+template <int NT, int R>
+__device__ __forceinline__ void row_round_fused(uint32_t* X, uint32_t L, const uint32_t* twf, const uint32_t* twi,
+                                                Mod md) {
+  static_assert(R <= 6, "group must lie inside one LDS row");
+  constexpr int E = 1 << R;
+  uint32_t wf[E - 1], wfn[E - 1], wi[E - 1];
+#pragma unroll
+  for (int k = 0; k < E - 1; k++) {
+    // entry k = 2^t - 1 + jj of stage t sits at table index 2^t + jj = k + 1
+    wf[k] = ldg(twf, (uint32_t)k + 1);
+    wi[k] = ldg(twi, (uint32_t)k + 1);
+    wfn[k] = md.P - wf[k];
+  }
+  for (uint32_t g = threadIdx.x; g < (L >> R); g += NT) {
+    const uint32_t pa = lds_at(g << R), pb = lds_at(L + (g << R));
+    uint32_t va[E], vb[E];
+#pragma unroll
+    for (int j = 0; j < E; j++) {
+      va[j] = X[pa ^ (uint32_t)j];
+      vb[j] = X[pb ^ (uint32_t)j];
+    }
+    dif_stages<R>(va, wf, wfn, md);
+    dif_stages<R>(vb, wf, wfn, md);
+#pragma unroll
+    for (int j = 0; j < E; j++) va[j] = mmul(va[j], vb[j], md);
+    dit_stages<R>(va, wi, md);
+#pragma unroll
+    for (int j = 0; j < E; j++) X[pa ^ (uint32_t)j] = va[j];
+  }
+  __syncthreads();
 }
 
 // Column tiles of a length-2^N transform: 2^(N-13) rows x 2^col_lc(N) columns.
@@ -413,16 +534,6 @@ __device__ __forceinline__ void col_stages(int n, int lc, uint32_t* X, uint32_t 
   }
 }
 
-// Stores whose data another workgroup reads later in the same persistent
-// launch are agent-scope atomic stores (global_store ... sc1): they are
-// written through to the device coherence point, so a consumer on another
-// XCD sees them once they have completed, and no L2 write-back is needed
-// when the task is published.
-template <bool COH>
-__device__ __forceinline__ void st_out(uint32_t* p, uint32_t v) {
-  if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  else *p = v;
-}
 
 // ---------------------------------------------------------------------------
 // Task bodies.  Every thread of the workgroup calls them (they contain
@@ -552,6 +663,20 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
                          uint32_t prescale, uint32_t* X) {
   const Mod md = mod_of(pr);
   const uint32_t L = 1u << lr;
+  if (mode == ROW_POLY && lr == kRowLog) {
+    // compile-time rounds: the first reads global memory, the last forward
+    // round, the pointwise product and the first inverse round run fused, the
+    // last writes global memory
+    constexpr int nr = fixed_nrounds<kRowLog, RM>();
+    static_assert(nr >= 3, "first, middle and last rounds must be distinct");
+    row_round_in<NT, fixed_rsize<kRowLog, RM>(0), fixed_dif_slo<kRowLog, RM>(0)>(X, L, gA, gB, pr.twf, md);
+    fixed_dif<NT, 2, RM, kRowLog, 0, 0, 1, nr - 1>(X, (int)L, 0u, pr.twf, md);
+    row_round_fused<NT, fixed_rsize<kRowLog, RM>(nr - 1)>(X, L, pr.twf, pr.twi, md);
+    fixed_dit<NT, RM, kRowLog, 0, 0, 1, nr - 1>(X, 0u, pr.twi, md);
+    row_round_out<NT, fixed_dit_rsize<kRowLog, RM>(nr - 1), fixed_dit_slo<kRowLog, RM>(nr - 1), COH>(X, gA, pr.twi, md);
+    __syncthreads();
+    return;
+  }
   if (mode == ROW_POLY && lr >= 2 && (((uintptr_t)gA | (uintptr_t)gB) & 15u) == 0) {
     // 128-bit loads of both blocks
     const v4u* a4 = reinterpret_cast<const v4u*>(gA);
@@ -578,8 +703,7 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
   }
   __syncthreads();
   if (lr > 0) {
-    if (mode == ROW_POLY && lr == kRowLog) fixed_dif<NT, 2, RM, kRowLog, 0, 0>(X, (int)L, 0u, pr.twf, md);
-    else if (mode == ROW_POLY) lds_dif<NT, 2, RM>(X, (int)L, lr, 0, 0, 0, pr.twf, md);
+    if (mode == ROW_POLY) lds_dif<NT, 2, RM>(X, (int)L, lr, 0, 0, 0, pr.twf, md);
     else if (mode == ROW_FWD) lds_dif<NT, 1, RM>(X, 0, lr, 0, 0, 0, pr.twf, md);
   }
   if (mode == ROW_POLY) {
