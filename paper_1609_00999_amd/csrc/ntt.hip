@@ -336,11 +336,27 @@ __device__ __forceinline__ void fill_group_addr(uint32_t* ad, uint32_t yb, uint3
   }
 }
 
+// Global operands of a column tile whose first and last rounds read and
+// write global memory directly.  Element (k, c) of the tile is global index
+// colbase + c + k 2^RS.
+struct ColIO {
+  const uint32_t* src;   // first round: residues, zero beyond index dvalid
+  uint32_t dvalid;
+  uint32_t scale;        // first round: nonzero multiplies by REDC(x * scale)
+  uint32_t* dst;         // last round: stores only indices < nout
+  uint32_t nout;
+};
+
 // One round with compile-time geometry: rows of 2^LC columns (LC = 0 for the
-// row pass), transform length 2^LR along rows, global row stride 2^RS.
-template <int NT, int NA, int R, bool INV, int LR, int LC, int RS, int S_LO>
+// row pass), transform length 2^LR along rows, global row stride 2^RS.  GIN:
+// the group is loaded from io.src instead of LDS; GOUT: it is stored to
+// io.dst (coherent stores if COH) instead of LDS.  With both, the round does
+// not touch LDS.
+template <int NT, int NA, int R, bool INV, int LR, int LC, int RS, int S_LO, bool GIN = false, bool GOUT = false,
+          bool COH = false>
 __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t colbase, const uint32_t* tw,
-                                                Mod md) {
+                                                Mod md, ColIO io = ColIO{}) {
+  static_assert(NA == 1 || !(GIN || GOUT), "global rounds take one operand");
   constexpr int E = 1 << R;
   constexpr int A_LO = S_LO + LC;
   constexpr uint32_t lomask = (1u << A_LO) - 1;
@@ -368,34 +384,62 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
       uint32_t v[E];
       uint32_t ad[E];
       fill_group_addr<A_LO, R, 0>(ad, yb, pb);
+      // global index of the group's element j
+      const uint32_t gi0 = colbase + c + ((base >> LC) << RS);
+      constexpr int GS = S_LO + RS;
+      if constexpr (GIN) {
 #pragma unroll
-      for (int j = 0; j < E; j++) v[j] = X[ad[j]];
+        for (int j = 0; j < E; j++) {
+          const uint32_t gi = gi0 + ((uint32_t)j << GS);
+          v[j] = gi <= io.dvalid ? io.src[gi] : 0u;
+        }
+        if (io.scale) {
+#pragma unroll
+          for (int j = 0; j < E; j++) v[j] = mmul(v[j], io.scale, md);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < E; j++) v[j] = X[ad[j]];
+      }
       if constexpr (!INV) dif_stages<R>(v, w, wn, md);
       else dit_stages<R>(v, w, md);
+      if constexpr (GOUT) {
 #pragma unroll
-      for (int j = 0; j < E; j++) X[ad[j]] = v[j];
+        for (int j = 0; j < E; j++) {
+          const uint32_t gi = gi0 + ((uint32_t)j << GS);
+          if (gi < io.nout) st_out<COH>(io.dst + gi, v[j]);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < E; j++) X[ad[j]] = v[j];
+      }
     }
   }
   __syncthreads();
 }
 
-// Forward rounds IDX .. END-1 (all of them by default).
-template <int NT, int NA, int RM, int LR, int LC, int RS, int IDX = 0, int END = fixed_nrounds<LR, RM>()>
-__device__ __forceinline__ void fixed_dif(uint32_t* X, int off, uint32_t colbase, const uint32_t* tw, Mod md) {
+// Forward rounds IDX .. END-1 (all of them by default).  GIO: round 0 loads
+// from and round END-1 stores to global memory (ColIO).
+template <int NT, int NA, int RM, int LR, int LC, int RS, int IDX = 0, int END = fixed_nrounds<LR, RM>(),
+          bool GIO = false, bool COH = false>
+__device__ __forceinline__ void fixed_dif(uint32_t* X, int off, uint32_t colbase, const uint32_t* tw, Mod md,
+                                          ColIO io = ColIO{}) {
   if constexpr (IDX < END) {
-    lds_round_fixed<NT, NA, fixed_rsize<LR, RM>(IDX), false, LR, LC, RS, fixed_dif_slo<LR, RM>(IDX)>(X, off, colbase,
-                                                                                                     tw, md);
-    fixed_dif<NT, NA, RM, LR, LC, RS, IDX + 1, END>(X, off, colbase, tw, md);
+    lds_round_fixed<NT, NA, fixed_rsize<LR, RM>(IDX), false, LR, LC, RS, fixed_dif_slo<LR, RM>(IDX), GIO && IDX == 0,
+                    GIO && IDX == END - 1, COH>(X, off, colbase, tw, md, io);
+    fixed_dif<NT, NA, RM, LR, LC, RS, IDX + 1, END, GIO, COH>(X, off, colbase, tw, md, io);
   }
 }
 
-// Inverse rounds IDX .. END-1 (all of them by default).
-template <int NT, int RM, int LR, int LC, int RS, int IDX = 0, int END = fixed_nrounds<LR, RM>()>
-__device__ __forceinline__ void fixed_dit(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+// Inverse rounds IDX .. END-1 (all of them by default), GIO as above.
+template <int NT, int RM, int LR, int LC, int RS, int IDX = 0, int END = fixed_nrounds<LR, RM>(), bool GIO = false,
+          bool COH = false>
+__device__ __forceinline__ void fixed_dit(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md,
+                                          ColIO io = ColIO{}) {
   if constexpr (IDX < END) {
-    lds_round_fixed<NT, 1, fixed_dit_rsize<LR, RM>(IDX), true, LR, LC, RS, fixed_dit_slo<LR, RM>(IDX)>(X, 0, colbase,
-                                                                                                       tw, md);
-    fixed_dit<NT, RM, LR, LC, RS, IDX + 1, END>(X, colbase, tw, md);
+    lds_round_fixed<NT, 1, fixed_dit_rsize<LR, RM>(IDX), true, LR, LC, RS, fixed_dit_slo<LR, RM>(IDX), GIO && IDX == 0,
+                    GIO && IDX == END - 1, COH>(X, 0, colbase, tw, md, io);
+    fixed_dit<NT, RM, LR, LC, RS, IDX + 1, END, GIO, COH>(X, colbase, tw, md, io);
   }
 }
 
@@ -505,33 +549,41 @@ __device__ __forceinline__ void row_round_fused(uint32_t* X, uint32_t L, const u
 
 constexpr int col_lc_c(int n) { return 13 < 14 - (n - 13) ? 13 : 14 - (n - 13); }
 
-template <int NT, int RM, int N>
-__device__ __forceinline__ void col_dif_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
-  fixed_dif<NT, 1, RM, N - 13, col_lc_c(N), 13>(X, 0, colbase, tw, md);
+// For 14 <= N <= 23 the column rounds are generated at compile time, the
+// first reading the tile from global memory and the last writing it there;
+// up to N = 17 a single round does both and the tile never passes through LDS.
+template <int NT, int RM, int N, bool COH>
+__device__ __forceinline__ void col_dif_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md, ColIO io) {
+  fixed_dif<NT, 1, RM, N - 13, col_lc_c(N), 13, 0, fixed_nrounds<N - 13, RM>(), true, COH>(X, 0, colbase, tw, md, io);
 }
 
-template <int NT, int RM, int N>
-__device__ __forceinline__ void col_dit_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
-  fixed_dit<NT, RM, N - 13, col_lc_c(N), 13>(X, colbase, tw, md);
+template <int NT, int RM, int N, bool COH>
+__device__ __forceinline__ void col_dit_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md, ColIO io) {
+  fixed_dit<NT, RM, N - 13, col_lc_c(N), 13, 0, fixed_nrounds<N - 13, RM>(), true, COH>(X, colbase, tw, md, io);
 }
 
-// Column stages for length 2^n: compile-time rounds for 14 <= n <= 23, the
-// general rounds otherwise.
-template <int NT, int RM, bool INV>
-__device__ __forceinline__ void col_stages(int n, int lc, uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+// Whole column tile (load, stages, store) for the compile-time lengths;
+// false, doing nothing, for the others.
+template <int NT, int RM, bool INV, bool COH>
+__device__ __forceinline__ bool col_fixed(int n, uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md, ColIO io) {
   switch (n) {
-#define MONT_COL(NN)                                                 \
-  case NN:                                                           \
-    if constexpr (INV) col_dit_fixed<NT, RM, NN>(X, colbase, tw, md); \
-    else col_dif_fixed<NT, RM, NN>(X, colbase, tw, md);              \
-    return;
+#define MONT_COL(NN)                                                         \
+  case NN:                                                                   \
+    if constexpr (INV) col_dit_fixed<NT, RM, NN, COH>(X, colbase, tw, md, io); \
+    else col_dif_fixed<NT, RM, NN, COH>(X, colbase, tw, md, io);              \
+    return true;
     MONT_COL(14) MONT_COL(15) MONT_COL(16) MONT_COL(17) MONT_COL(18)
     MONT_COL(19) MONT_COL(20) MONT_COL(21) MONT_COL(22) MONT_COL(23)
 #undef MONT_COL
-    default:
-      if constexpr (INV) lds_dit<NT, RM>(X, n - kRowLog, lc, kRowLog, colbase, tw, md);
-      else lds_dif<NT, 1, RM>(X, 0, n - kRowLog, lc, kRowLog, colbase, tw, md);
+    default: return false;
   }
+}
+
+// Column stages on an LDS tile for the other lengths (run-time rounds).
+template <int NT, int RM, bool INV>
+__device__ __forceinline__ void col_stages(int n, int lc, uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+  if constexpr (INV) lds_dit<NT, RM>(X, n - kRowLog, lc, kRowLog, colbase, tw, md);
+  else lds_dif<NT, 1, RM>(X, 0, n - kRowLog, lc, kRowLog, colbase, tw, md);
 }
 
 
@@ -572,6 +624,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
   const uint32_t colbase = t << lc;
   const uint32_t cnt = 1u << (n1 + lc);
   const uint32_t cmask = (1u << lc) - 1;
+  if (col_fixed<NT, RM, false, COH>(n, X, colbase, pr.twf, md, ColIO{src, dvalid, scale, dst, 0xFFFFFFFFu})) return;
   if (lc >= 2 && ((uintptr_t)src & 15u) == 0) {
     // rows of C >= 4 adjacent residues: 128-bit loads where all four are
     // inside the operand, element loads on the (at most one) straddling chunk
@@ -625,6 +678,7 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
   const uint32_t colbase = t << lc;
   const uint32_t cnt = 1u << (n1 + lc);
   const uint32_t cmask = (1u << lc) - 1;
+  if (col_fixed<NT, RM, true, false>(n, X, colbase, pr.twi, md, ColIO{src, 0xFFFFFFFFu, 0u, dst, nout})) return;
   if (lc >= 2 && ((uintptr_t)src & 15u) == 0) {
     // rows of C >= 4 adjacent residues: 128-bit loads
     for (uint32_t e4 = threadIdx.x; e4 < (cnt >> 2); e4 += NT) {
@@ -823,7 +877,9 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
   for (;;) {
     if (threadIdx.x == 0) s_task = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
-    const uint32_t ti = s_task;
+    // uniform across the workgroup: keeps the task's fields and pointers in
+    // scalar registers
+    const uint32_t ti = __builtin_amdgcn_readfirstlane(s_task);
     if (ti >= g.ntasks) break;
     const uint2 tk = g.tasks[ti];
     const uint32_t p = tk.x;
