@@ -264,8 +264,9 @@ def cpu_model():
     return "unknown"
 
 
-def timed(torch, fn, reps=5):
-    fn()
+def timed(torch, fn, reps=5, warmup=1):
+    for _ in range(warmup):
+        fn()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -579,7 +580,8 @@ def polymul_batch_extra(torch, wl, dev):
     # split products and execute fewer (ntt_plan_work)
     redc = sum(polymul_redc_count(int(a), int(b)) for a, b in zip(batch.da, batch.db))
     executed, nsplit = plan.work()
-    t_batch = timed(torch, lambda: plan.execute(din, dout, scr), 5)
+    # a few batches first: the clocks settle over the first tens of milliseconds
+    t_batch = timed(torch, lambda: plan.execute(din, dout, scr), 5, warmup=3)
     st = plan.status(scr)
     got = dout.cpu().numpy().view(np.uint32)
     rng = np.random.default_rng(5)
@@ -598,7 +600,7 @@ def polymul_batch_extra(torch, wl, dev):
     torch.cuda.current_stream().wait_stream(s)
     with torch.cuda.graph(g):
         plan.execute(din, dout, scr)
-    t_graph = timed(torch, g.replay, 5)
+    t_graph = timed(torch, g.replay, 5, warmup=3)
     # per-product plain launches
     big = max(ntt.scratch_bytes(int(a), int(b)) for a, b in zip(batch.da, batch.db))
     pscr = torch.empty(max(1, big // 4), dtype=torch.int32, device=dev)
