@@ -66,7 +66,7 @@ def test_context_roots_and_tables(ctx):
             assert int(iv[x]) == pow(root, (1 << lmax) - e, P) * R % P, (pid, x)
 
 
-@pytest.mark.parametrize("logn", [0, 1, 2, 5, 10, 12, 13, 14, 15, 17, 20, 23])
+@pytest.mark.parametrize("logn", [0, 1, 2, 5, 10, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23])
 def test_forward_inverse_vs_oracle(N, ctx, logn):
     pid = logn % len(PRIMES)
     P = PRIMES[pid]
@@ -143,16 +143,17 @@ def test_polymul_special_cases(N, ctx):
     assert got.tolist() == [math.comb(2 * dd, k) % P for k in range(2 * dd + 1)]
 
 
-def test_polymul_largest_length(N, ctx):
-    """N = 2^23, the longest transform the tables support: Schwartz-Zippel."""
-    d = (1 << 22) - 1
+@pytest.mark.parametrize("da,db", [((1 << 22) - 1, (1 << 22) - 1), (1500000, 1500000), ((1 << 21) - 1, 1 << 20)])
+def test_polymul_largest_length(N, ctx, da, db):
+    """N = 2^23, the longest transform the tables support, and N = 2^22
+    (column tiles of 32 columns): Schwartz-Zippel."""
     pid = 1
     P = PRIMES[pid]
-    rng = np.random.default_rng(23)
-    a = rng.integers(0, P, d + 1, dtype=np.uint32)
-    b = rng.integers(0, P, d + 1, dtype=np.uint32)
+    rng = np.random.default_rng(da + db)
+    a = rng.integers(0, P, da + 1, dtype=np.uint32)
+    b = rng.integers(0, P, db + 1, dtype=np.uint32)
     c = host(N.polymul(ctx, pid, dev(a), dev(b)))
-    assert c.size == 2 * d + 1
+    assert c.size == da + db + 1
     for x in rng.integers(2, P, 3).tolist():
         assert oracle.horner(P, c, x) == oracle.horner(P, a, x) * oracle.horner(P, b, x) % P
 
@@ -287,6 +288,29 @@ def test_batch_config_full_size(N, ctx):
     jobs = [batch.operands(i) for i in sample]
     for i, ref in zip(sample, oracle.polymul_many(jobs)):
         assert np.array_equal(got[batch.c_off[i]: batch.c_off[i] + ref.size], ref), i
+
+
+def test_batch_longest_lengths(N, ctx):
+    """One persistent launch holding unsplit products of transform lengths
+    2^22 and 2^23 (the longest compile-time column tiles) beside short ones:
+    Schwartz-Zippel at three points per product."""
+    # none of these meets the split rule: the top product would be longer than N/4
+    da = np.array([1500000, (1 << 22) - 1, (1 << 21) - 1, 3000, 120000, 14000], dtype=np.int64)
+    db = np.array([1500000, (1 << 22) - 1, 1 << 20, 2000, 120000, 14100], dtype=np.int64)
+    rng = np.random.default_rng(2223)
+    pid = rng.integers(0, len(PRIMES), da.size)
+    batch = wl.pack_products(PRIMES, pid, da, db, rng)
+    plan = N.Plan.from_batch(ctx, batch)
+    executed, nsplit = plan.work()
+    plan.close()
+    assert nsplit == 0
+    st, got = run_plan(N, ctx, batch)
+    assert st == 0
+    for i in range(batch.count):
+        P, a, b = batch.operands(i)
+        c = got[batch.c_off[i]: batch.c_off[i] + a.size + b.size - 1]
+        for x in rng.integers(2, P, 3).tolist():
+            assert oracle.horner(P, c, x) == oracle.horner(P, a, x) * oracle.horner(P, b, x) % P, i
 
 
 def test_batch_graph_replay(N, ctx):
