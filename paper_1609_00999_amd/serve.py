@@ -19,6 +19,7 @@ and test doubles.
 from __future__ import annotations
 
 import collections
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -104,7 +105,7 @@ class Scheduler:
     """FIFO admission by footprint into free slots; one batch per slot."""
 
     def __init__(self, executor, slots: int = 4, budget_bytes: int = 16 << 30, max_batch: int = 256,
-                 clock=time.perf_counter, idle_sleep: float = 0.0):
+                 clock=time.perf_counter, idle_sleep: float = 0.0, pause_gc: bool = True):
         if slots < 1 or budget_bytes <= 0 or max_batch < 1:
             raise ValueError("slots, budget and max_batch must be positive")
         self.ex = executor
@@ -113,8 +114,22 @@ class Scheduler:
         self.max_batch = max_batch
         self.clock = clock
         self.idle_sleep = idle_sleep
+        # Python's cyclic collector can stop the loop for milliseconds when a
+        # full collection walks every live request; reference counting still
+        # frees what the loop drops, and the collector resumes afterwards.
+        self.pause_gc = pause_gc
 
     def run(self, jobs: list) -> RunStats:
+        was_enabled = gc.isenabled()
+        if self.pause_gc:
+            gc.disable()
+        try:
+            return self._run(jobs)
+        finally:
+            if self.pause_gc and was_enabled:
+                gc.enable()
+
+    def _run(self, jobs: list) -> RunStats:
         jobs = sorted(jobs, key=lambda j: (j.t_arrival, j.rid))
         for j in jobs:
             if j.footprint <= 0:
