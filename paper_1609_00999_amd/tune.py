@@ -62,9 +62,14 @@ def merge(cache: dict, arch: str, family: str, bucket: str, entry: dict) -> dict
     return cache
 
 
-def best_entry(results):
-    """results: list of (config, seconds); the fastest, with every measurement."""
+def best_entry(results, tie: float = 0.0, cost=None):
+    """results: list of (config, seconds); the fastest, with every measurement.
+    With tie > 0, among the configs within that fraction of the fastest time
+    the one of least cost(config) wins (ties keep the fastest)."""
     cfg, sec = min(results, key=lambda r: r[1])
+    if tie > 0 and cost is not None:
+        close = [r for r in results if r[1] <= sec * (1 + tie)]
+        cfg, sec = min(close, key=lambda r: (cost(r[0]), r[1]))
     return {"config": list(cfg), "seconds": sec, "measured": [[list(c), s] for c, s in results]}
 
 
@@ -162,7 +167,10 @@ def tune_ntt(batch=None, reps: int = 3):
             mont.check(L.ntt_tune_set(threads, radix, gm), "ntt_tune_set")
             t = _time(torch, lambda: plan.execute(din, dout, scr), reps)
             res.append(((threads, radix, gm), t))
-    best = best_entry(res)
+    # A larger grid multiplier only adds workgroups that find the queue empty;
+    # within 1 % of the fastest batch the smaller grid wins, since it costs
+    # less launch latency when a batch is small (a serving loop).
+    best = best_entry(res, tie=0.01, cost=lambda c: c[2])
     mont.check(L.ntt_tune_set(*best["config"]), "ntt_tune_set")
     plan.close()
     ctx.close()

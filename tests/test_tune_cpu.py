@@ -32,6 +32,18 @@ def test_best_entry_and_choose(tmp_path):
     assert tune.load(os.path.join(str(tmp_path), "missing.json")) == {}
 
 
+def test_best_entry_tie_prefers_the_cheaper_config():
+    # the transform tuner's rule: within 1 % of the fastest, the smaller grid multiplier
+    res = [((512, 4, 1), 9.413), ((512, 4, 2), 9.394), ((512, 3, 1), 10.03), ((256, 4, 1), 9.40)]
+    e = tune.best_entry(res, tie=0.01, cost=lambda c: c[2])
+    assert e["config"] == [256, 4, 1] and e["seconds"] == 9.40     # cheapest, then fastest
+    e = tune.best_entry(res[:3], tie=0.01, cost=lambda c: c[2])
+    assert e["config"] == [512, 4, 1]
+    e = tune.best_entry(res[:3], tie=0.001, cost=lambda c: c[2])
+    assert e["config"] == [512, 4, 2]                              # outside the tie band
+    assert tune.best_entry(res)["config"] == [512, 4, 2]           # no tie rule: fastest
+
+
 def test_apply_uses_the_c_abi():
     cache = {"gfx950": {"elem_mul": {"28": {"config": [512, 2, 1]}}, "ntt": {"batch2048": {"config": [1024, 3, 2]}}}}
     lib = FakeLib()
