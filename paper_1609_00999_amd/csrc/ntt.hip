@@ -23,6 +23,9 @@
 // 2^13 in memory) and a row pass over contiguous blocks of 2^13 (the last 13
 // stages).  A polynomial product fuses the forward row pass of both operands,
 // the pointwise product and the first 13 inverse stages into one row task.
+// In row blocks and in column tiles of lengths 2^14..2^23 the first register
+// round reads its groups from HBM and the last writes them back, so the
+// blocks are not staged through LDS on the way in or out.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -134,6 +137,17 @@ __device__ __forceinline__ uint32_t ldg(const uint32_t* p, uint32_t i) {
   return ((gptr_u32)p)[i];
 }
 
+// The lane's index in the workgroup as the task bodies use it.  The empty asm
+// makes each read opaque, so what a task derives from it (group bases, LDS
+// addresses) is computed inside the persistent task loop rather than hoisted
+// out of it and held in registers across every task variant, which pushed
+// the persistent kernel past its register budget into spills.
+__device__ __forceinline__ uint32_t task_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Stores whose data another workgroup reads later in the same persistent
 // launch are agent-scope atomic stores (global_store ... sc1): they are
 // written through to the device coherence point, so a consumer on another
@@ -197,7 +211,7 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
   const int a_lo = s_lo + lc;                      // LDS address bit of stage s_lo
   const uint32_t lomask = (1u << a_lo) - 1;
   const uint32_t ngroups = M >> R;
-  for (uint32_t g = threadIdx.x; g < ngroups; g += NT) {
+  for (uint32_t g = task_tid(); g < ngroups; g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);   // zero in bits a_lo .. a_lo+R-1
     const uint32_t c = base & ((1u << lc) - 1);
     const uint32_t kb = base >> lc;
@@ -361,7 +375,7 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
   constexpr int A_LO = S_LO + LC;
   constexpr uint32_t lomask = (1u << A_LO) - 1;
   constexpr uint32_t ngroups = (1u << (LR + LC)) >> R;
-  for (uint32_t g = threadIdx.x; g < ngroups; g += NT) {
+  for (uint32_t g = task_tid(); g < ngroups; g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
     const uint32_t c = base & ((1u << LC) - 1);
     const uint32_t t0 = colbase + c + (((base >> LC) & ((1u << S_LO) - 1)) << RS);
@@ -456,7 +470,7 @@ __device__ __forceinline__ void row_round_in(uint32_t* X, uint32_t L, const uint
   static_assert(S_LO >= 9, "the group stride must be above the swizzled bits");
   constexpr int E = 1 << R;
   constexpr uint32_t lomask = (1u << S_LO) - 1;
-  for (uint32_t g = threadIdx.x; g < ((1u << kRowLog) >> R); g += NT) {
+  for (uint32_t g = task_tid(); g < ((1u << kRowLog) >> R); g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
     const uint32_t* twg = tw + (base & lomask);
     uint32_t w[E - 1], wn[E - 1];
@@ -486,7 +500,7 @@ __device__ __forceinline__ void row_round_out(const uint32_t* X, uint32_t* gA, c
   static_assert(S_LO >= 9, "the group stride must be above the swizzled bits");
   constexpr int E = 1 << R;
   constexpr uint32_t lomask = (1u << S_LO) - 1;
-  for (uint32_t g = threadIdx.x; g < ((1u << kRowLog) >> R); g += NT) {
+  for (uint32_t g = task_tid(); g < ((1u << kRowLog) >> R); g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
     const uint32_t* twg = tw + (base & lomask);
     uint32_t w[E - 1];
@@ -526,7 +540,7 @@ __device__ __forceinline__ void row_round_fused(uint32_t* X, uint32_t L, const u
     wi[k] = ldg(twi, (uint32_t)k + 1);
     wfn[k] = md.P - wf[k];
   }
-  for (uint32_t g = threadIdx.x; g < (L >> R); g += NT) {
+  for (uint32_t g = task_tid(); g < (L >> R); g += NT) {
     const uint32_t pa = lds_at(g << R), pb = lds_at(L + (g << R));
     uint32_t va[E], vb[E];
 #pragma unroll
@@ -552,36 +566,46 @@ constexpr int col_lc_c(int n) { return 13 < 14 - (n - 13) ? 13 : 14 - (n - 13); 
 // For 14 <= N <= 23 the column rounds are generated at compile time, the
 // first reading the tile from global memory and the last writing it there;
 // up to N = 17 a single round does both and the tile never passes through LDS.
-template <int NT, int RM, int N, bool COH>
-__device__ __forceinline__ void col_dif_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md, ColIO io) {
-  fixed_dif<NT, 1, RM, N - 13, col_lc_c(N), 13, 0, fixed_nrounds<N - 13, RM>(), true, COH>(X, 0, colbase, tw, md, io);
+template <int NT, int RM, int N, bool GIO, bool COH>
+__device__ __forceinline__ void col_dif_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md,
+                                              ColIO io = ColIO{}) {
+  fixed_dif<NT, 1, RM, N - 13, col_lc_c(N), 13, 0, fixed_nrounds<N - 13, RM>(), GIO, COH>(X, 0, colbase, tw, md, io);
 }
 
-template <int NT, int RM, int N, bool COH>
-__device__ __forceinline__ void col_dit_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md, ColIO io) {
-  fixed_dit<NT, RM, N - 13, col_lc_c(N), 13, 0, fixed_nrounds<N - 13, RM>(), true, COH>(X, colbase, tw, md, io);
+template <int NT, int RM, int N, bool GIO, bool COH>
+__device__ __forceinline__ void col_dit_fixed(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md,
+                                              ColIO io = ColIO{}) {
+  fixed_dit<NT, RM, N - 13, col_lc_c(N), 13, 0, fixed_nrounds<N - 13, RM>(), GIO, COH>(X, colbase, tw, md, io);
 }
 
-// Whole column tile (load, stages, store) for the compile-time lengths;
-// false, doing nothing, for the others.
+// Whole column tile (load, stages, store) with HBM first and last rounds, for
+// 2^15..2^23; false, doing nothing, for the others.  A 2^14 tile (two rows of
+// 2^13) is a single radix-2 round whose sixteen groups per lane would each
+// wait on HBM in turn; it is staged through LDS with wide loads instead.
 template <int NT, int RM, bool INV, bool COH>
 __device__ __forceinline__ bool col_fixed(int n, uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md, ColIO io) {
   switch (n) {
-#define MONT_COL(NN)                                                         \
-  case NN:                                                                   \
-    if constexpr (INV) col_dit_fixed<NT, RM, NN, COH>(X, colbase, tw, md, io); \
-    else col_dif_fixed<NT, RM, NN, COH>(X, colbase, tw, md, io);              \
+#define MONT_COL(NN)                                                               \
+  case NN:                                                                         \
+    if constexpr (INV) col_dit_fixed<NT, RM, NN, true, COH>(X, colbase, tw, md, io); \
+    else col_dif_fixed<NT, RM, NN, true, COH>(X, colbase, tw, md, io);              \
     return true;
-    MONT_COL(14) MONT_COL(15) MONT_COL(16) MONT_COL(17) MONT_COL(18)
+    MONT_COL(15) MONT_COL(16) MONT_COL(17) MONT_COL(18)
     MONT_COL(19) MONT_COL(20) MONT_COL(21) MONT_COL(22) MONT_COL(23)
 #undef MONT_COL
     default: return false;
   }
 }
 
-// Column stages on an LDS tile for the other lengths (run-time rounds).
+// Column stages on an LDS tile for the other lengths: compile-time rounds
+// for 2^14, run-time rounds otherwise.
 template <int NT, int RM, bool INV>
 __device__ __forceinline__ void col_stages(int n, int lc, uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+  if (n == 14) {
+    if constexpr (INV) col_dit_fixed<NT, RM, 14, false, false>(X, colbase, tw, md);
+    else col_dif_fixed<NT, RM, 14, false, false>(X, colbase, tw, md);
+    return;
+  }
   if constexpr (INV) lds_dit<NT, RM>(X, n - kRowLog, lc, kRowLog, colbase, tw, md);
   else lds_dif<NT, 1, RM>(X, 0, n - kRowLog, lc, kRowLog, colbase, tw, md);
 }
@@ -601,16 +625,16 @@ __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const
   const Mod md = mod_of(pr);
   const uint32_t N = 1u << n;
   const uint32_t sc = pr.s2[n];
-  for (uint32_t e = threadIdx.x; e < N; e += NT) {
+  for (uint32_t e = task_tid(); e < N; e += NT) {
     X[lds_at(e)] = e <= da ? a[e] : 0u;
     X[lds_at(N + e)] = e <= db ? mmul(b[e], sc, md) : 0u;
   }
   __syncthreads();
   if (n > 0) lds_dif<NT, 2, RM>(X, (int)N, n, 0, 0, 0, pr.twf, md);
-  for (uint32_t e = threadIdx.x; e < N; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(N + e)], md);
+  for (uint32_t e = task_tid(); e < N; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(N + e)], md);
   __syncthreads();
   if (n > 0) lds_dit<NT, RM>(X, n, 0, 0, 0, pr.twi, md);
-  for (uint32_t e = threadIdx.x; e < nout; e += NT) out[e] = X[lds_at(e)];
+  for (uint32_t e = task_tid(); e < nout; e += NT) out[e] = X[lds_at(e)];
   __syncthreads();
 }
 
@@ -628,7 +652,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
   if (lc >= 2 && ((uintptr_t)src & 15u) == 0) {
     // rows of C >= 4 adjacent residues: 128-bit loads where all four are
     // inside the operand, element loads on the (at most one) straddling chunk
-    for (uint32_t e4 = threadIdx.x; e4 < (cnt >> 2); e4 += NT) {
+    for (uint32_t e4 = task_tid(); e4 < (cnt >> 2); e4 += NT) {
       const uint32_t e = e4 << 2;
       const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
       v4u v;
@@ -652,7 +676,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
       X[lds_at(e + 3)] = v.w;
     }
   } else {
-    for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+    for (uint32_t e = task_tid(); e < cnt; e += NT) {
       const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
       uint32_t v = i <= dvalid ? src[i] : 0u;
       if (scale) v = mmul(v, scale, md);
@@ -661,7 +685,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
   }
   __syncthreads();
   col_stages<NT, RM, false>(n, lc, X, colbase, pr.twf, md);
-  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+  for (uint32_t e = task_tid(); e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     st_out<COH>(dst + i, X[lds_at(e)]);
   }
@@ -681,7 +705,7 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
   if (col_fixed<NT, RM, true, false>(n, X, colbase, pr.twi, md, ColIO{src, 0xFFFFFFFFu, 0u, dst, nout})) return;
   if (lc >= 2 && ((uintptr_t)src & 15u) == 0) {
     // rows of C >= 4 adjacent residues: 128-bit loads
-    for (uint32_t e4 = threadIdx.x; e4 < (cnt >> 2); e4 += NT) {
+    for (uint32_t e4 = task_tid(); e4 < (cnt >> 2); e4 += NT) {
       const uint32_t e = e4 << 2;
       const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
       const v4u v = *reinterpret_cast<const v4u*>(src + i);
@@ -691,14 +715,14 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
       X[lds_at(e + 3)] = v.w;
     }
   } else {
-    for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+    for (uint32_t e = task_tid(); e < cnt; e += NT) {
       const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
       X[lds_at(e)] = src[i];
     }
   }
   __syncthreads();
   col_stages<NT, RM, true>(n, lc, X, colbase, pr.twi, md);
-  for (uint32_t e = threadIdx.x; e < cnt; e += NT) {
+  for (uint32_t e = task_tid(); e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     if (i < nout) dst[i] = X[lds_at(e)];
   }
@@ -735,7 +759,7 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
     // 128-bit loads of both blocks
     const v4u* a4 = reinterpret_cast<const v4u*>(gA);
     const v4u* b4 = reinterpret_cast<const v4u*>(gB);
-    for (uint32_t e4 = threadIdx.x; e4 < (L >> 2); e4 += NT) {
+    for (uint32_t e4 = task_tid(); e4 < (L >> 2); e4 += NT) {
       const v4u va = a4[e4], vb = b4[e4];
       const uint32_t e = e4 << 2;
       X[lds_at(e)] = va.x;
@@ -748,7 +772,7 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
       X[lds_at(L + e + 3)] = vb.w;
     }
   } else {
-    for (uint32_t e = threadIdx.x; e < L; e += NT) {
+    for (uint32_t e = task_tid(); e < L; e += NT) {
       uint32_t v = gA[e];
       if (mode == ROW_INV && prescale) v = mmul(v, prescale, md);
       X[lds_at(e)] = v;
@@ -761,12 +785,12 @@ __device__ __forceinline__ void exec_row(const PrimeDev& pr, int lr, int mode, u
     else if (mode == ROW_FWD) lds_dif<NT, 1, RM>(X, 0, lr, 0, 0, 0, pr.twf, md);
   }
   if (mode == ROW_POLY) {
-    for (uint32_t e = threadIdx.x; e < L; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(L + e)], md);
+    for (uint32_t e = task_tid(); e < L; e += NT) X[lds_at(e)] = mmul(X[lds_at(e)], X[lds_at(L + e)], md);
     __syncthreads();
   }
   if (mode != ROW_FWD && lr == kRowLog) fixed_dit<NT, RM, kRowLog, 0, 0>(X, 0u, pr.twi, md);
   else if (mode != ROW_FWD && lr > 0) lds_dit<NT, RM>(X, lr, 0, 0, 0, pr.twi, md);
-  for (uint32_t e = threadIdx.x; e < L; e += NT) st_out<COH>(gA + e, X[lds_at(e)]);
+  for (uint32_t e = task_tid(); e < L; e += NT) st_out<COH>(gA + e, X[lds_at(e)]);
   __syncthreads();
 }
 
