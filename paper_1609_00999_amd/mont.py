@@ -362,12 +362,13 @@ class Batch:
         self._keep = items
         check(lib().mont_batch_update(self.handle, arr, len(items), stream_handle()), "mont_batch_update")
 
-    def update_raw(self, descs):
-        """descs: a ctypes array of VecDesc (pointers already resolved)."""
-        check(lib().mont_batch_update(self.handle, descs, len(descs), stream_handle()), "mont_batch_update")
+    def update_raw(self, descs, stream=None):
+        """descs: a ctypes array of VecDesc (pointers already resolved); uploaded
+        on `stream` (the current stream if None)."""
+        check(lib().mont_batch_update(self.handle, descs, len(descs), stream_handle(stream)), "mont_batch_update")
 
-    def mul(self):
-        check(lib().mont_batch_mul(self.handle, stream_handle()), "mont_batch_mul")
+    def mul(self, stream=None):
+        check(lib().mont_batch_mul(self.handle, stream_handle(stream)), "mont_batch_mul")
 
 
 ELEM_OPS = {"to": 0, "from": 1, "mul": 2, "muladd": 3, "pow": 4, "modmul": 5}

@@ -212,12 +212,13 @@ class Plan:
         """A reusable plan (ntt_plan_reserve); fill it with update()."""
         return cls(ctx, None, None, None, None, None, None, _reserve=(max_products, max_tasks))
 
-    def update(self, descs: np.ndarray, order_seed: int = 0):
-        """Replan for a new batch (structured array of DESC_DTYPE), uploaded on the current stream."""
+    def update(self, descs: np.ndarray, order_seed: int = 0, stream=None):
+        """Replan for a new batch (structured array of DESC_DTYPE), uploaded on
+        `stream` (a torch stream; the current stream if None)."""
         descs = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
         self._descs = descs
         mont.check(mont.lib().ntt_plan_update(self.handle, descs.ctypes.data if len(descs) else None, len(descs),
-                                              order_seed, mont.stream_handle()), "ntt_plan_update")
+                                              order_seed, mont.stream_handle(stream)), "ntt_plan_update")
         self._info()
 
     def work(self):
@@ -255,7 +256,8 @@ class Plan:
         torch = _torch()
         return torch.empty(max(1, (self.scratch_bytes + 3) // 4), dtype=torch.int32, device=device)
 
-    def execute(self, coeffs_in, out, scratch, grid: int = 0, spin_limit: int = 0):
+    def execute(self, coeffs_in, out, scratch, grid: int = 0, spin_limit: int = 0, stream=None):
+        """One launch of the whole batch on `stream` (the current stream if None)."""
         if coeffs_in.numel() < self.in_words or out.numel() < self.out_words:
             raise ValueError("input or output buffer shorter than the plan needs")
         if scratch.numel() * scratch.element_size() < self.scratch_bytes:
@@ -263,7 +265,7 @@ class Plan:
         mont.check(mont.lib().ntt_plan_execute(self.handle, mont.dev_ptr(coeffs_in, "coeffs_in"),
                                                mont.dev_ptr(out, "out"), mont.dev_ptr(scratch, "scratch"),
                                                scratch.numel() * scratch.element_size(), grid, spin_limit,
-                                               mont.stream_handle()), "ntt_plan_execute")
+                                               mont.stream_handle(stream)), "ntt_plan_execute")
         return out
 
     def status(self, scratch) -> int:

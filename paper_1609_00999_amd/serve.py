@@ -313,53 +313,56 @@ class GpuBatchExecutor:
         muls = [j for j in batch if j.kind == "mul"]
         polys = [j for j in batch if j.kind == "polymul"]
         dev = self.inputs.arena.device
-        with torch.cuda.stream(s):
-            plan, desc, cpos = None, None, 0
-            if polys:
-                desc = np.zeros(len(polys), dtype=ntt.DESC_DTYPE)
-                for i, j in enumerate(polys):
-                    a0, b0, n = self.inputs.offs[j.rid]
-                    desc[i] = (j.prime_id, j.size, j.size, 0, a0, b0, cpos)
-                    cpos += 2 * j.size + 1
-                plan = self.plans[slot]
-                plan.update(desc)
-            scr_words = (plan.scratch_bytes + 3) // 4 if plan is not None else 0
-            need = sum(_a4(j.size) for j in muls) + (_a4(cpos) + _a4(scr_words) if polys else 0)
-            arena = self.arenas[slot] if need <= self.arena_words else None
+        # Every library call below names the slot's stream explicitly: looking
+        # up torch's current stream costs more host time than the call itself.
+        plan, desc, cpos = None, None, 0
+        if polys:
+            desc = np.zeros(len(polys), dtype=ntt.DESC_DTYPE)
+            for i, j in enumerate(polys):
+                a0, b0, n = self.inputs.offs[j.rid]
+                desc[i] = (j.prime_id, j.size, j.size, 0, a0, b0, cpos)
+                cpos += 2 * j.size + 1
+            plan = self.plans[slot]
+            plan.update(desc, stream=s)
+        scr_words = (plan.scratch_bytes + 3) // 4 if plan is not None else 0
+        need = sum(_a4(j.size) for j in muls) + (_a4(cpos) + _a4(scr_words) if polys else 0)
+        arena = self.arenas[slot] if need <= self.arena_words else None
+        if arena is None:
+            self.fallback_batches += 1
+        pos = 0
+
+        def take(nw):
+            nonlocal pos
             if arena is None:
-                self.fallback_batches += 1
-            pos = 0
-
-            def take(nw):
-                nonlocal pos
-                if arena is None:
+                with torch.cuda.stream(s):
                     return torch.empty(max(1, nw), dtype=torch.int32, device=dev)
-                v = arena[pos:pos + max(1, nw)]
-                pos += _a4(max(1, nw))
-                return v
+            v = arena[pos:pos + max(1, nw)]
+            pos += _a4(max(1, nw))
+            return v
 
-            keep = []
-            if muls:
-                descs = (mont.VecDesc * len(muls))()
-                for i, j in enumerate(muls):
-                    a, b = self.inputs.views(j.rid)
-                    out = take(j.size)
-                    prm = self.params[j.prime_id]
-                    descs[i] = mont.VecDesc(a.data_ptr(), b.data_ptr(), out.data_ptr(), j.size, prm.P, prm.Pprime)
-                    j.result = out
-                    keep.append(out)
-                self.vecb[slot].update_raw(descs)
-                self.vecb[slot].mul()
-            if polys:
-                out = take(cpos)
-                scr = take(scr_words)
-                plan.execute(self.inputs.arena, out, scr)
-                keep += [out, scr]
-                for i, j in enumerate(polys):
-                    c0 = int(desc["c_off"][i])
-                    j.result = out[c0:c0 + 2 * j.size + 1]
-            ev = torch.cuda.Event()
-            ev.record(s)
+        keep = []
+        if muls:
+            descs = (mont.VecDesc * len(muls))()
+            base = self.inputs.arena.data_ptr()
+            for i, j in enumerate(muls):
+                a0, b0, _ = self.inputs.offs[j.rid]
+                out = take(j.size)
+                prm = self.params[j.prime_id]
+                descs[i] = mont.VecDesc(base + 4 * a0, base + 4 * b0, out.data_ptr(), j.size, prm.P, prm.Pprime)
+                j.result = out
+                keep.append(out)
+            self.vecb[slot].update_raw(descs, stream=s)
+            self.vecb[slot].mul(stream=s)
+        if polys:
+            out = take(cpos)
+            scr = take(scr_words)
+            plan.execute(self.inputs.arena, out, scr, stream=s)
+            keep += [out, scr]
+            for i, j in enumerate(polys):
+                c0 = int(desc["c_off"][i])
+                j.result = out[c0:c0 + 2 * j.size + 1]
+        ev = torch.cuda.Event()
+        ev.record(s)
         return (ev, batch, keep, slot, arena is not None)
 
     def poll(self, handle) -> bool:
