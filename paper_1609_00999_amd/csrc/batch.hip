@@ -83,26 +83,26 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch_mul(const VecDev* vecs,
 
 using namespace mont;
 
+// The descriptors and the contiguous array of the vectors' first tiles share
+// one device block (and one pinned staging block), so an update is one copy:
+// count VecDev records, then count uint64 tile starts.
 struct mont_batch {
   int cap = 0;
   int count = 0;
   uint64_t ntiles = 0;
-  VecDev* d_vecs = nullptr;
-  VecDev* h_vecs = nullptr;       // pinned staging
-  uint64_t* d_begin = nullptr;    // tile_begin of every vector, contiguous
-  uint64_t* h_begin = nullptr;
+  void* d_block = nullptr;
+  void* h_block = nullptr;        // pinned staging
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   int grid = 0;
 };
+static_assert(sizeof(VecDev) % 8 == 0, "the tile starts follow the descriptors 8-byte aligned");
 
 namespace {
 
 void free_batch(mont_batch* b) {
-  (void)hipFree(b->d_vecs);
-  (void)hipFree(b->d_begin);
-  if (b->h_vecs) (void)hipHostFree(b->h_vecs);
-  if (b->h_begin) (void)hipHostFree(b->h_begin);
+  (void)hipFree(b->d_block);
+  if (b->h_block) (void)hipHostFree(b->h_block);
   if (b->staged) (void)hipEventDestroy(b->staged);
   delete b;
 }
@@ -115,10 +115,9 @@ extern "C" mont_status mont_batch_reserve(int max_vectors, mont_batch** out) {
   mont_batch* b = new (std::nothrow) mont_batch;
   if (!b) return MONT_ENOMEM;
   b->cap = max_vectors;
-  if (hipMalloc(&b->d_vecs, sizeof(VecDev) * max_vectors) != hipSuccess ||
-      hipMalloc(&b->d_begin, sizeof(uint64_t) * max_vectors) != hipSuccess ||
-      hipHostMalloc((void**)&b->h_vecs, sizeof(VecDev) * max_vectors, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&b->h_begin, sizeof(uint64_t) * max_vectors, hipHostMallocDefault) != hipSuccess ||
+  const size_t bytes = (sizeof(VecDev) + sizeof(uint64_t)) * (size_t)max_vectors;
+  if (hipMalloc(&b->d_block, bytes) != hipSuccess ||
+      hipHostMalloc(&b->h_block, bytes, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) {
     free_batch(b);
     return MONT_ENOMEM;
@@ -141,16 +140,18 @@ extern "C" mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* des
   }
   if (b->staged_pending && hipEventSynchronize(b->staged) != hipSuccess) return MONT_EHIP;
   b->staged_pending = false;
+  VecDev* hv = static_cast<VecDev*>(b->h_block);
+  uint64_t* hbeg = reinterpret_cast<uint64_t*>(hv + count);
   uint64_t tiles = 0;
   for (int i = 0; i < count; i++) {
     const mont_vec_desc& d = descs[i];
-    VecDev& v = b->h_vecs[i];
+    VecDev& v = hv[i];
     v.a = d.a;
     v.b = d.b;
     v.out = d.out;
     v.n = d.n;
     v.tile_begin = tiles;
-    b->h_begin[i] = tiles;
+    hbeg[i] = tiles;
     v.P = d.P;
     v.Pp = d.Pprime;
     tiles += (d.n + kBatchTile - 1) / kBatchTile;
@@ -159,8 +160,8 @@ extern "C" mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* des
   b->ntiles = tiles;
   if (count > 0) {
     hipStream_t s = as_stream(stream);
-    if (hipMemcpyAsync(b->d_vecs, b->h_vecs, sizeof(VecDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(b->d_begin, b->h_begin, sizeof(uint64_t) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+    if (hipMemcpyAsync(b->d_block, b->h_block, (sizeof(VecDev) + sizeof(uint64_t)) * count, hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
         hipEventRecord(b->staged, s) != hipSuccess)
       return MONT_EHIP;
     b->staged_pending = true;
@@ -173,8 +174,9 @@ extern "C" mont_status mont_batch_mul(const mont_batch* b, void* stream) {
   if (b->count == 0 || b->ntiles == 0) return MONT_OK;
   (void)hipGetLastError();
   uint64_t grid = b->ntiles < (uint64_t)b->grid ? b->ntiles : (uint64_t)b->grid;
-  hipLaunchKernelGGL(k_batch_mul, dim3((unsigned)grid), dim3(kBatchThreads), 0, as_stream(stream), b->d_vecs,
-                     b->d_begin, (uint32_t)b->count, b->ntiles);
+  const VecDev* dv = static_cast<const VecDev*>(b->d_block);
+  hipLaunchKernelGGL(k_batch_mul, dim3((unsigned)grid), dim3(kBatchThreads), 0, as_stream(stream), dv,
+                     reinterpret_cast<const uint64_t*>(dv + b->count), (uint32_t)b->count, b->ntiles);
   return last_launch_status();
 }
 

@@ -83,6 +83,8 @@ struct FixDev {
   uint32_t chunk0;          // first of its ceil(m / kFixChunk) chunks in the fix-up launch
 };
 constexpr uint32_t kFixChunk = 1024;
+// A reusable plan uploads products, fix-ups and tasks back to back in one block.
+static_assert(sizeof(ProdDev) % 16 == 0 && sizeof(FixDev) % 16 == 0, "records keep the block 16-byte aligned");
 
 enum TaskKind : uint32_t { T_SMALL = 0, T_COLF_A = 1, T_COLF_B = 2, T_ROW = 3, T_COLI = 4 };
 
@@ -1104,14 +1106,16 @@ struct ntt_plan {
   uint64_t redc = 0;        // REDC one execution performs
   FixDev* d_fix = nullptr;
   int default_grid = 0;
-  // Reusable plans (ntt_plan_reserve): device capacity and pinned staging
-  // for asynchronous updates; `staged` marks the last upload from staging.
+  // Reusable plans (ntt_plan_reserve): one device block and one pinned
+  // staging block of the same capacity.  An update packs its products, fix-ups
+  // and tasks back to back into staging and uploads them with one copy;
+  // d_prods, d_fix and d_tasks then point into the device block.  `staged`
+  // marks the last upload from staging.
   bool reusable = false;
   int cap_prods = 0;        // caller's products; internal capacity is twice that
   uint32_t cap_tasks = 0;
-  ProdDev* h_prods = nullptr;
-  uint2* h_tasks = nullptr;
-  FixDev* h_fix = nullptr;
+  void* d_block = nullptr;
+  void* h_block = nullptr;
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
 };
@@ -1607,14 +1611,23 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
 }
 
 void free_plan(ntt_plan* plan) {
-  (void)hipFree(plan->d_prods);
-  (void)hipFree(plan->d_tasks);
-  (void)hipFree(plan->d_fix);
-  if (plan->h_prods) (void)hipHostFree(plan->h_prods);
-  if (plan->h_tasks) (void)hipHostFree(plan->h_tasks);
-  if (plan->h_fix) (void)hipHostFree(plan->h_fix);
+  if (plan->reusable) {
+    (void)hipFree(plan->d_block);
+    if (plan->h_block) (void)hipHostFree(plan->h_block);
+  } else {
+    (void)hipFree(plan->d_prods);
+    (void)hipFree(plan->d_tasks);
+    (void)hipFree(plan->d_fix);
+  }
   if (plan->staged) (void)hipEventDestroy(plan->staged);
   delete plan;
+}
+
+// Bytes of a reusable plan's block: 2 max_products product descriptors (a
+// split product has two parts), max_products fix-ups, max_tasks tasks.
+size_t plan_block_bytes(int max_products, uint32_t max_tasks) {
+  return sizeof(ProdDev) * 2 * (size_t)max_products + sizeof(FixDev) * (size_t)max_products +
+         sizeof(uint2) * (size_t)max_tasks;
 }
 
 }  // namespace
@@ -1673,13 +1686,9 @@ extern "C" mont_status ntt_plan_reserve(const ntt_ctx* ctx, int max_products, ui
   plan->reusable = true;
   plan->cap_prods = max_products;
   plan->cap_tasks = max_tasks;
-  const size_t nint = 2 * (size_t)max_products;    // a split product has two parts
-  if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * nint) != hipSuccess ||
-      hipMalloc(&plan->d_tasks, sizeof(uint2) * max_tasks) != hipSuccess ||
-      hipMalloc(&plan->d_fix, sizeof(FixDev) * max_products) != hipSuccess ||
-      hipHostMalloc((void**)&plan->h_prods, sizeof(ProdDev) * nint, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&plan->h_tasks, sizeof(uint2) * max_tasks, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&plan->h_fix, sizeof(FixDev) * max_products, hipHostMallocDefault) != hipSuccess ||
+  const size_t bytes = plan_block_bytes(max_products, max_tasks);
+  if (hipMalloc(&plan->d_block, bytes) != hipSuccess ||
+      hipHostMalloc(&plan->h_block, bytes, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming) != hipSuccess) {
     free_plan(plan);
     return MONT_ENOMEM;
@@ -1708,18 +1717,22 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   plan->staged_pending = false;
   hipStream_t s = as_stream(stream);
   if (!prods.empty()) {
-    std::memcpy(plan->h_prods, prods.data(), sizeof(ProdDev) * prods.size());
-    if (!tasks.empty()) std::memcpy(plan->h_tasks, tasks.data(), sizeof(uint2) * tasks.size());
-    if (!fixes.empty()) std::memcpy(plan->h_fix, fixes.data(), sizeof(FixDev) * fixes.size());
-    if (hipMemcpyAsync(plan->d_prods, plan->h_prods, sizeof(ProdDev) * prods.size(), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        (!tasks.empty() && hipMemcpyAsync(plan->d_tasks, plan->h_tasks, sizeof(uint2) * tasks.size(),
-                                          hipMemcpyHostToDevice, s) != hipSuccess) ||
-        (!fixes.empty() && hipMemcpyAsync(plan->d_fix, plan->h_fix, sizeof(FixDev) * fixes.size(),
-                                          hipMemcpyHostToDevice, s) != hipSuccess) ||
+    // products, fix-ups, tasks back to back (every record size is a multiple
+    // of 8 bytes), one upload
+    const size_t bp = sizeof(ProdDev) * prods.size(), bf = sizeof(FixDev) * fixes.size(),
+                 bt = sizeof(uint2) * tasks.size();
+    char* h = static_cast<char*>(plan->h_block);
+    char* d = static_cast<char*>(plan->d_block);
+    std::memcpy(h, prods.data(), bp);
+    if (bf) std::memcpy(h + bp, fixes.data(), bf);
+    if (bt) std::memcpy(h + bp + bf, tasks.data(), bt);
+    if (hipMemcpyAsync(d, h, bp + bf + bt, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipEventRecord(plan->staged, s) != hipSuccess)
       return MONT_EHIP;
     plan->staged_pending = true;
+    plan->d_prods = reinterpret_cast<ProdDev*>(d);
+    plan->d_fix = reinterpret_cast<FixDev*>(d + bp);
+    plan->d_tasks = reinterpret_cast<uint2*>(d + bp + bf);
   }
   plan->count = (int)prods.size();
   plan->ntasks = (uint32_t)tasks.size();
