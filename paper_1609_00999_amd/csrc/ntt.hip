@@ -1444,6 +1444,10 @@ uint32_t product_tasks(int n) {
 
 // Groups of multi-pass products in the task pipeline of a plan.
 constexpr int kPipeGroups = 8;
+// Batches with fewer multi-pass products than this are ordered phase by phase
+// (the software pipeline pays only when many products overlap; a serving
+// loop's batches of a few dozen products finish sooner without it).
+constexpr size_t kPipeMinProducts = 128;
 
 size_t product_task_total(const std::vector<ProdDev>& prods) {
   size_t t = 0;
@@ -1542,22 +1546,54 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   }
   for (int p = 0; p < np; p++)
     if (prods[p].n <= (uint32_t)kRowLog) small.push_back(make_uint2((uint32_t)p, T_SMALL << 28));
-  // Multi-pass products, longest first, cut into kPipeGroups groups of about
-  // equal work.  The list is a software pipeline over the groups: block b
-  // interleaves the row blocks of group b-1 (bound by the vector ALU) with the
-  // forward column tiles of group b and the inverse column tiles of group b-2
-  // (bound by memory latency), so the two workgroups of a CU tend to hold
-  // tasks of both kinds.  Every prerequisite still precedes its dependants:
-  // the forward tiles of a group come in an earlier block than its rows, and
-  // its rows in an earlier block than its inverse tiles.
   std::vector<int> big;
   for (int p = 0; p < np; p++)
     if (prods[p].n > (uint32_t)kRowLog) big.push_back(p);
   std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return prods[x].n > prods[y].n; });
   std::stable_sort(small.begin(), small.end(), [&](uint2 x, uint2 y) { return prods[x.x].n > prods[y.x].n; });
+  tasks.reserve(product_task_total(prods));
+  std::mt19937_64 rng(order_seed);
+  if (big.size() < kPipeMinProducts) {
+    // Phase order: every forward column tile (longest products first), half
+    // the single-task products, every row block, the other half, every
+    // inverse column tile.  A batch of a few multi-pass products finishes
+    // soonest this way: its longest product's tasks are not spread out behind
+    // other products' tasks.
+    std::vector<uint2> colf, row, coli;
+    for (int p : big) {
+      const ProdDev& pd = prods[p];
+      for (uint32_t t = 0; t < pd.ntiles; t++) colf.push_back(make_uint2((uint32_t)p, (T_COLF_A << 28) | t));
+      for (uint32_t t = 0; t < pd.ntiles; t++) colf.push_back(make_uint2((uint32_t)p, (T_COLF_B << 28) | t));
+      for (uint32_t j = 0; j < pd.nblocks; j++) row.push_back(make_uint2((uint32_t)p, (T_ROW << 28) | j));
+      for (uint32_t t = 0; t < pd.ntiles; t++) coli.push_back(make_uint2((uint32_t)p, (T_COLI << 28) | t));
+    }
+    if (order_seed != 0) {
+      // Any order within a phase keeps prerequisites earlier in the list.
+      std::shuffle(colf.begin(), colf.end(), rng);
+      std::shuffle(small.begin(), small.end(), rng);
+      std::shuffle(row.begin(), row.end(), rng);
+      std::shuffle(coli.begin(), coli.end(), rng);
+    }
+    const size_t half = small.size() / 2;
+    tasks.insert(tasks.end(), colf.begin(), colf.end());
+    tasks.insert(tasks.end(), small.begin(), small.begin() + half);
+    tasks.insert(tasks.end(), row.begin(), row.end());
+    tasks.insert(tasks.end(), small.begin() + half, small.end());
+    tasks.insert(tasks.end(), coli.begin(), coli.end());
+    scr_words = scr;
+    return MONT_OK;
+  }
+  // Many multi-pass products: longest first, cut into kPipeGroups groups of
+  // about equal work.  The list is a software pipeline over the groups: block
+  // b interleaves the row blocks of group b-1 (bound by the vector ALU) with
+  // the forward column tiles of group b and the inverse column tiles of group
+  // b-2 (bound by memory latency), so the two workgroups of a CU tend to hold
+  // tasks of both kinds.  Every prerequisite still precedes its dependants:
+  // the forward tiles of a group come in an earlier block than its rows, and
+  // its rows in an earlier block than its inverse tiles.
   double total = 0;
   for (int p : big) total += std::ldexp(1.0, (int)prods[p].n) * prods[p].n;
-  const int ng = big.empty() ? 0 : kPipeGroups;
+  const int ng = kPipeGroups;
   std::vector<std::vector<uint2>> colf_g(ng), row_g(ng), coli_g(ng);
   double acc = 0;
   for (int p : big) {
@@ -1575,7 +1611,6 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   for (size_t i = 0; i < small.size(); i++) small_b[i * nblk / small.size()].push_back(small[i]);
   if (order_seed != 0) {
     // Any order within a list keeps prerequisites earlier in the whole list.
-    std::mt19937_64 rng(order_seed);
     for (int g = 0; g < ng; g++) {
       std::shuffle(colf_g[g].begin(), colf_g[g].end(), rng);
       std::shuffle(row_g[g].begin(), row_g[g].end(), rng);
@@ -1583,7 +1618,6 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
     }
     for (auto& v : small_b) std::shuffle(v.begin(), v.end(), rng);
   }
-  tasks.reserve(product_task_total(prods));
   // Block b (0 .. ng+1) holds the forward tiles of group b, the rows of group
   // b-1, the inverse tiles of group b-2 and a share of the single tasks,
   // merged in proportion to their lengths.

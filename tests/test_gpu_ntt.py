@@ -230,6 +230,19 @@ def test_batch_grid_and_order_invariance(N, ctx):
         assert o.tobytes() == outs[0].tobytes()
 
 
+def test_batch_pipelined_order(N, ctx):
+    """A batch with enough multi-pass products for the software-pipelined
+    task order (smaller batches are ordered phase by phase): exact for several
+    grids and shuffled orders within the pipeline's lists."""
+    batch = small_batch(160, 13, 15, 43)
+    assert int(np.sum(batch.da + batch.db + 1 > 8192)) >= 128
+    ref = oracle_batch(batch)
+    for grid, seed in [(0, 0), (3, 0), (0, 777)]:
+        st, got = run_plan(N, ctx, batch, grid=grid, order_seed=seed)
+        assert st == 0
+        assert np.array_equal(got, ref), (grid, seed)
+
+
 def test_batch_empty_and_tiny(N, ctx):
     b = wl.pack_products(PRIMES, [0], [0], [0], np.random.default_rng(0))
     st, got = run_plan(N, ctx, b)
