@@ -203,9 +203,9 @@ MONT_API mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* descs
 
 /*
  * mont_batch_mul -- Algorithm 2 elementwise over every vector of the batch in
- * ONE persistent launch: out_i[j] = REDC(a_i[j] * b_i[j]) modulo P_i.  The
- * work is cut into tiles of 4096 residues that never straddle two vectors.
- * Operands are residues in [0, P_i).
+ * ONE launch: out_i[j] = REDC(a_i[j] * b_i[j]) modulo P_i.  The work is cut
+ * into tiles of 4096 residues that never straddle two vectors, one workgroup
+ * per tile.  Operands are residues in [0, P_i).
  */
 MONT_API mont_status mont_batch_mul(const mont_batch* b, void* stream);
 

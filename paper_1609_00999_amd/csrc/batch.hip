@@ -1,6 +1,6 @@
 // batch.hip -- Montgomery products over a batch of vectors of uneven
-// lengths, each with its own modulus, in one persistent launch
-// (Algorithm 2 of arXiv:1609.00999, section 3.1, elementwise).
+// lengths, each with its own modulus, in one launch (Algorithm 2 of
+// arXiv:1609.00999, section 3.1, elementwise).
 #include <hip/hip_runtime.h>
 
 #include <new>
@@ -16,11 +16,12 @@ __device__ __forceinline__ bool aligned16_dev(const void* p) { return ((uintptr_
 
 // ---------------------------------------------------------------------------
 // Batches of vectors of uneven lengths, each with its own modulus, in one
-// persistent launch.  The flattened work is cut into tiles of kBatchTile
-// residues that never straddle two vectors: vector v owns tiles
-// [tile_begin[v], tile_begin[v+1]).  A workgroup finds its tile's vector by
-// binary search and streams that tile with 128-bit accesses when the
-// vector's arrays are 16-byte aligned.
+// launch.  The flattened work is cut into tiles of kBatchTile residues that
+// never straddle two vectors: vector v owns tiles [tile_begin[v],
+// tile_begin[v+1]).  One workgroup takes one tile (workgroups stride over the
+// tiles only beyond 2^20 of them), finds the tile's vector by binary search
+// and streams it with 128-bit accesses when the vector's arrays are 16-byte
+// aligned.
 // ---------------------------------------------------------------------------
 
 constexpr int kBatchThreads = 256;
