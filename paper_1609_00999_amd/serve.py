@@ -262,8 +262,9 @@ class DeviceInputs:
 
 
 class GpuBatchExecutor:
-    """Runs each admitted batch as one persistent launch for its elementwise
-    requests and one for its polynomial products, on the slot's stream."""
+    """Runs each admitted batch as one vector-batch launch for its elementwise
+    requests and one persistent launch for its polynomial products, on the
+    slot's stream."""
 
     def __init__(self, ctx, inputs: DeviceInputs, slots: int, max_batch: int, keep_results: bool = True,
                  max_tasks: int = 1 << 20, arena_bytes: int = 1 << 30):
