@@ -1552,7 +1552,6 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return prods[x].n > prods[y].n; });
   std::stable_sort(small.begin(), small.end(), [&](uint2 x, uint2 y) { return prods[x.x].n > prods[y.x].n; });
   tasks.reserve(product_task_total(prods));
-  std::mt19937_64 rng(order_seed);
   if (big.size() < kPipeMinProducts) {
     // Phase order: every forward column tile (longest products first), half
     // the single-task products, every row block, the other half, every
@@ -1569,6 +1568,7 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
     }
     if (order_seed != 0) {
       // Any order within a phase keeps prerequisites earlier in the list.
+      std::mt19937_64 rng(order_seed);
       std::shuffle(colf.begin(), colf.end(), rng);
       std::shuffle(small.begin(), small.end(), rng);
       std::shuffle(row.begin(), row.end(), rng);
@@ -1611,6 +1611,7 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   for (size_t i = 0; i < small.size(); i++) small_b[i * nblk / small.size()].push_back(small[i]);
   if (order_seed != 0) {
     // Any order within a list keeps prerequisites earlier in the whole list.
+    std::mt19937_64 rng(order_seed);
     for (int g = 0; g < ng; g++) {
       std::shuffle(colf_g[g].begin(), colf_g[g].end(), rng);
       std::shuffle(row_g[g].begin(), row_g[g].end(), rng);
