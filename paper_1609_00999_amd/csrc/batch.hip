@@ -37,44 +37,74 @@ struct VecDev {
   uint32_t P, Pp;
 };
 
+// One tile: kBatchTile residues of vector v starting at its tile t.
+__device__ __forceinline__ void batch_tile(const VecDev& v, uint64_t t) {
+  const Mod md{v.P, v.Pp};
+  const uint64_t e0 = (t - v.tile_begin) * kBatchTile;
+  const uint64_t e1 = e0 + kBatchTile < v.n ? e0 + kBatchTile : v.n;
+  const bool al = aligned16_dev(v.a) && aligned16_dev(v.b) && aligned16_dev(v.out);
+  if (al && e1 - e0 == kBatchTile) {
+    const v4u* va = reinterpret_cast<const v4u*>(v.a + e0);
+    const v4u* vb = reinterpret_cast<const v4u*>(v.b + e0);
+    v4u* vo = reinterpret_cast<v4u*>(v.out + e0);
+    v4u x[kBatchVpt], y[kBatchVpt];
+#pragma unroll
+    for (int j = 0; j < kBatchVpt; j++) {
+      x[j] = __builtin_nontemporal_load(va + j * kBatchThreads + threadIdx.x);
+      y[j] = __builtin_nontemporal_load(vb + j * kBatchThreads + threadIdx.x);
+    }
+#pragma unroll
+    for (int j = 0; j < kBatchVpt; j++) {
+      v4u r;
+      r.x = mmul(x[j].x, y[j].x, md);
+      r.y = mmul(x[j].y, y[j].y, md);
+      r.z = mmul(x[j].z, y[j].z, md);
+      r.w = mmul(x[j].w, y[j].w, md);
+      __builtin_nontemporal_store(r, vo + j * kBatchThreads + threadIdx.x);
+    }
+  } else {
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBatchThreads) v.out[e] = mmul(v.a[e], v.b[e], md);
+  }
+}
+
+// Last v < nvec with begin[v] <= t (begin[0] = 0 <= t).
+template <typename BEGIN>
+__device__ __forceinline__ uint32_t tile_owner(const BEGIN& begin, uint32_t nvec, uint64_t t) {
+  uint32_t lo = 0, hi = nvec - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (begin[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // tile_begin[v] repeats vecs[v].tile_begin in a contiguous array, so the
 // binary search touches a few cache lines instead of one descriptor each.
 __global__ __launch_bounds__(kBatchThreads) void k_batch_mul(const VecDev* vecs, const uint64_t* tile_begin,
                                                              uint32_t nvec, uint64_t ntiles) {
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) batch_tile(vecs[tile_owner(tile_begin, nvec, t)], t);
+}
+
+// Small batches pass their descriptors by value in the kernel arguments, so
+// a launch needs no upload before it: a serving loop's batches hold one or
+// two vectors, and the host-to-device copy of their descriptors cost more
+// latency than the products.
+constexpr int kInlineVecs = 16;
+struct InlineVecs {
+  VecDev v[kInlineVecs];
+  uint32_t nvec;
+};
+
+struct InlineBegin {
+  const InlineVecs& iv;
+  __device__ uint64_t operator[](uint32_t i) const { return iv.v[i].tile_begin; }
+};
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch_mul_inline(InlineVecs iv, uint64_t ntiles) {
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    uint32_t lo = 0, hi = nvec - 1;             // last v with tile_begin[v] <= t
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (tile_begin[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const VecDev v = vecs[lo];
-    const Mod md{v.P, v.Pp};
-    const uint64_t e0 = (t - v.tile_begin) * kBatchTile;
-    const uint64_t e1 = e0 + kBatchTile < v.n ? e0 + kBatchTile : v.n;
-    const bool al = aligned16_dev(v.a) && aligned16_dev(v.b) && aligned16_dev(v.out);
-    if (al && e1 - e0 == kBatchTile) {
-      const v4u* va = reinterpret_cast<const v4u*>(v.a + e0);
-      const v4u* vb = reinterpret_cast<const v4u*>(v.b + e0);
-      v4u* vo = reinterpret_cast<v4u*>(v.out + e0);
-      v4u x[kBatchVpt], y[kBatchVpt];
-#pragma unroll
-      for (int j = 0; j < kBatchVpt; j++) {
-        x[j] = __builtin_nontemporal_load(va + j * kBatchThreads + threadIdx.x);
-        y[j] = __builtin_nontemporal_load(vb + j * kBatchThreads + threadIdx.x);
-      }
-#pragma unroll
-      for (int j = 0; j < kBatchVpt; j++) {
-        v4u r;
-        r.x = mmul(x[j].x, y[j].x, md);
-        r.y = mmul(x[j].y, y[j].y, md);
-        r.z = mmul(x[j].z, y[j].z, md);
-        r.w = mmul(x[j].w, y[j].w, md);
-        __builtin_nontemporal_store(r, vo + j * kBatchThreads + threadIdx.x);
-      }
-    } else {
-      for (uint64_t e = e0 + threadIdx.x; e < e1; e += kBatchThreads) v.out[e] = mmul(v.a[e], v.b[e], md);
-    }
+    const uint32_t o = tile_owner(InlineBegin{iv}, iv.nvec, t);
+    batch_tile(iv.v[o], t);
   }
 }
 
@@ -96,6 +126,7 @@ struct mont_batch {
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   int grid = 0;
+  InlineVecs inl;                 // the descriptors of a batch of at most kInlineVecs vectors
 };
 static_assert(sizeof(VecDev) % 8 == 0, "the tile starts follow the descriptors 8-byte aligned");
 
@@ -159,6 +190,12 @@ extern "C" mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* des
   }
   b->count = count;
   b->ntiles = tiles;
+  if (count > 0 && count <= kInlineVecs) {
+    // launched with the descriptors by value: nothing to upload
+    for (int i = 0; i < count; i++) b->inl.v[i] = hv[i];
+    b->inl.nvec = (uint32_t)count;
+    return MONT_OK;
+  }
   if (count > 0) {
     hipStream_t s = as_stream(stream);
     if (hipMemcpyAsync(b->d_block, b->h_block, (sizeof(VecDev) + sizeof(uint64_t)) * count, hipMemcpyHostToDevice,
@@ -175,6 +212,11 @@ extern "C" mont_status mont_batch_mul(const mont_batch* b, void* stream) {
   if (b->count == 0 || b->ntiles == 0) return MONT_OK;
   (void)hipGetLastError();
   uint64_t grid = b->ntiles < (uint64_t)b->grid ? b->ntiles : (uint64_t)b->grid;
+  if (b->count <= kInlineVecs) {
+    hipLaunchKernelGGL(k_batch_mul_inline, dim3((unsigned)grid), dim3(kBatchThreads), 0, as_stream(stream), b->inl,
+                       b->ntiles);
+    return last_launch_status();
+  }
   const VecDev* dv = static_cast<const VecDev*>(b->d_block);
   hipLaunchKernelGGL(k_batch_mul, dim3((unsigned)grid), dim3(kBatchThreads), 0, as_stream(stream), dv,
                      reinterpret_cast<const uint64_t*>(dv + b->count), (uint32_t)b->count, b->ntiles);

@@ -66,6 +66,32 @@ def test_vector_batch_uneven(mods):
     b.close()
 
 
+def test_vector_batch_large_and_small_in_turn(mods):
+    """Batches above 16 vectors upload their descriptors; smaller ones pass
+    them in the launch.  One object alternates between the two."""
+    mont = mods[0]
+    rng = np.random.default_rng(7)
+    sizes = [int(x) for x in rng.integers(0, 20000, 40)] + [0, 1, 4096, 70000]
+    b = mont.Batch(len(sizes))
+    items, refs = [], []
+    for i, n in enumerate(sizes):
+        P = PRIMES[i % len(PRIMES)]
+        prm = mont.setup(P)
+        a = rng.integers(0, P, n, dtype=np.uint32)
+        c = rng.integers(0, P, n, dtype=np.uint32)
+        out = torch.empty(max(1, n), dtype=torch.int32, device="cuda")[:n]
+        items.append((prm, dev(a), dev(c), out))
+        refs.append(oracle.mont_mul(P, a, c))
+    for sel in (slice(0, 44), slice(40, 43), slice(3, 44), slice(41, 42), slice(0, 17), slice(0, 16)):
+        for _, _, _, out in items[sel]:
+            out.zero_()
+        b.update(items[sel])
+        b.mul()
+        for (_, _, _, out), ref in zip(items[sel], refs[sel]):
+            assert np.array_equal(host(out), ref), sel
+    b.close()
+
+
 def test_vector_batch_errors(mods):
     mont = mods[0]
     b = mont.Batch(2)
