@@ -193,11 +193,12 @@ typedef struct mont_batch mont_batch;
 MONT_API mont_status mont_batch_reserve(int max_vectors, mont_batch** out);
 
 /*
- * mont_batch_update -- loads `count` host descriptors and uploads them
- * asynchronously on `stream` (launches that use them go on the same stream,
- * after this call).  Blocks only until the previous upload has left the
- * staging buffer.  Errors: MONT_EINVAL (bad modulus pair, NULL pointer with
- * n > 0), MONT_ERANGE (count above the reserved capacity), MONT_EHIP.
+ * mont_batch_update -- loads `count` host descriptors.  Up to 16 are kept on
+ * the host and passed to the kernel in its launch arguments; more are
+ * uploaded asynchronously on `stream` (launches that use them go on the same
+ * stream, after this call).  Blocks only until the previous upload has left
+ * the staging buffer.  Errors: MONT_EINVAL (bad modulus pair, NULL pointer
+ * with n > 0), MONT_ERANGE (count above the reserved capacity), MONT_EHIP.
  */
 MONT_API mont_status mont_batch_update(mont_batch* b, const mont_vec_desc* descs, int count, void* stream);
 
