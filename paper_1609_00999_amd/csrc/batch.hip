@@ -69,7 +69,7 @@ __device__ __forceinline__ void batch_tile(const VecDev& v, uint64_t t) {
 
 // Last v < nvec with begin[v] <= t (begin[0] = 0 <= t).
 template <typename BEGIN>
-__device__ __forceinline__ uint32_t tile_owner(const BEGIN& begin, uint32_t nvec, uint64_t t) {
+__device__ __forceinline__ uint32_t tile_owner(BEGIN begin, uint32_t nvec, uint64_t t) {
   uint32_t lo = 0, hi = nvec - 1;
   while (lo < hi) {
     const uint32_t mid = (lo + hi + 1) >> 1;
@@ -83,7 +83,10 @@ __device__ __forceinline__ uint32_t tile_owner(const BEGIN& begin, uint32_t nvec
 // binary search touches a few cache lines instead of one descriptor each.
 __global__ __launch_bounds__(kBatchThreads) void k_batch_mul(const VecDev* vecs, const uint64_t* tile_begin,
                                                              uint32_t nvec, uint64_t ntiles) {
-  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) batch_tile(vecs[tile_owner(tile_begin, nvec, t)], t);
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const VecDev v = vecs[tile_owner(tile_begin, nvec, t)];
+    batch_tile(v, t);
+  }
 }
 
 // Small batches pass their descriptors by value in the kernel arguments, so
