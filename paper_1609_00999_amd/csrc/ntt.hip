@@ -856,6 +856,11 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_direct(Di
 // so every wait is on a task some running workgroup already holds.  Waits are
 // bounded by spin_limit sleeps; on expiry the status word is set, the task is
 // skipped, and so are all later waits, so the grid always drains.
+// A small plan (a serving loop's batch) travels in the launch arguments, so
+// its execution needs no upload before the launch.
+constexpr uint32_t kInlineProds = 4;
+constexpr uint32_t kInlineTasks = 384;
+
 struct PlanArgs {
   const PrimeDev* primes;
   const ProdDev* prods;
@@ -866,6 +871,9 @@ struct PlanArgs {
   uint32_t* out;
   uint32_t* scr;            // header, two counters per product, then product scratch
   uint32_t spin_limit;
+  uint32_t inl;             // 1: products and tasks are the copies below, not prods / tasks
+  ProdDev inl_prods[kInlineProds];
+  uint2 inl_tasks[kInlineTasks];
 };
 
 // Spin (lane 0 only) until *ctr >= need.  The loop reads the counter with
@@ -907,11 +915,11 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
     // scalar registers
     const uint32_t ti = __builtin_amdgcn_readfirstlane(s_task);
     if (ti >= g.ntasks) break;
-    const uint2 tk = g.tasks[ti];
+    const uint2 tk = g.inl ? g.inl_tasks[ti] : g.tasks[ti];
     const uint32_t p = tk.x;
     const uint32_t kind = tk.y >> 28;
     const uint32_t idx = tk.y & 0x0FFFFFFFu;
-    const ProdDev pd = g.prods[p];
+    const ProdDev pd = g.inl ? g.inl_prods[p] : g.prods[p];
     const PrimeDev& pr = g.primes[pd.prime_id];
     const uint32_t N = 1u << pd.n;
     uint32_t* scr = g.scr + pd.scr_off;
@@ -1118,6 +1126,11 @@ struct ntt_plan {
   void* h_block = nullptr;
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
+  // A reusable plan of at most kInlineProds internal products, kInlineTasks
+  // tasks and no fix-ups keeps them here and passes them in the launch.
+  bool inl = false;
+  ProdDev inl_prods[kInlineProds];
+  uint2 inl_tasks[kInlineTasks];
 };
 
 namespace {
@@ -1751,7 +1764,12 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   if (plan->staged_pending && hipEventSynchronize(plan->staged) != hipSuccess) return MONT_EHIP;
   plan->staged_pending = false;
   hipStream_t s = as_stream(stream);
-  if (!prods.empty()) {
+  plan->inl = !prods.empty() && prods.size() <= kInlineProds && tasks.size() <= kInlineTasks && fixes.empty();
+  if (plan->inl) {
+    // small enough for the launch arguments: nothing to upload
+    std::copy(prods.begin(), prods.end(), plan->inl_prods);
+    std::copy(tasks.begin(), tasks.end(), plan->inl_tasks);
+  } else if (!prods.empty()) {
     // products, fix-ups, tasks back to back (every record size is a multiple
     // of 8 bytes), one upload
     const size_t bp = sizeof(ProdDev) * prods.size(), bf = sizeof(FixDev) * fixes.size(),
@@ -1823,6 +1841,11 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   g.primes = plan->ctx->d_primes;
   g.prods = plan->d_prods;
   g.tasks = plan->d_tasks;
+  g.inl = plan->inl ? 1u : 0u;
+  if (plan->inl) {
+    std::copy(plan->inl_prods, plan->inl_prods + plan->count, g.inl_prods);
+    std::copy(plan->inl_tasks, plan->inl_tasks + plan->ntasks, g.inl_tasks);
+  }
   g.ntasks = plan->ntasks;
   g.nprods = (uint32_t)plan->count;
   g.in = d_in;
