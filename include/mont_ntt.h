@@ -137,8 +137,10 @@ MONT_API uint32_t ntt_plan_task_count(uint32_t da, uint32_t db);
  * ntt_plan_update -- replans a reserved plan for a new batch (same rules and
  * task order as ntt_plan_create) and uploads it asynchronously on `stream`;
  * executions of the plan must be enqueued on the same stream, after this
- * call, so that they see the new lists.  Blocks only until the previous
- * update's upload has left the staging buffers.  Errors: MONT_EINVAL (not a
+ * call, so that they see the new lists.  A plan of at most 4 internal
+ * products, 384 tasks and no split products is not uploaded: its lists travel
+ * in the arguments of each execution's launch.  Blocks only until the
+ * previous update's upload has left the staging buffers.  Errors: MONT_EINVAL (not a
  * reserved plan, bad descriptor), MONT_ERANGE (beyond the reserved capacity,
  * or a product too long), MONT_ENOROOT, MONT_EHIP.
  */
