@@ -111,7 +111,10 @@ def test_reserved_plan_updates(mods, ctx):
     ntt = mods[1]
     rng = np.random.default_rng(2)
     plan = ntt.Plan.reserve(ctx, 64, 1 << 16)
-    for rep, (lo, hi, count) in enumerate([(2, 16, 40), (10, 18, 12), (0, 6, 64)]):
+    # batches of at most 4 products (and no split ones) travel in the launch
+    # arguments, larger ones are uploaded: alternate between the two
+    shapes = [(2, 16, 40), (12, 16, 3), (10, 18, 12), (13, 14, 1), (0, 6, 64), (8, 12, 4), (14, 17, 2)]
+    for rep, (lo, hi, count) in enumerate(shapes):
         da = wl.log_uniform(rng, lo, hi, count)
         pid = rng.integers(0, len(PRIMES), count)
         batch = wl.pack_products(PRIMES, pid, da, da, rng)
