@@ -7,8 +7,10 @@
  *   c_abi_demo host   -- host-only calls: section 3.1 precomputation, the CRT
  *                        constants and error statuses (no GPU needed);
  *   c_abi_demo device -- device buffers from hipMalloc: conversion, product
- *                        and mul-add chains, a polynomial product and 64-bit
- *                        products, each compared with the oracle.
+ *                        and mul-add chains, a polynomial product, 64-bit
+ *                        products, vector batches and reusable plans (small
+ *                        enough for the launch arguments and not), each
+ *                        compared with the oracle.
  * Prints one line per check and exits 0 only if all pass.
  */
 #include <hip/hip_runtime_api.h>
@@ -24,6 +26,7 @@
 
 /* oracle (liboracle.so) */
 int orc_setup(uint32_t P, int r, uint32_t out[5]);
+void orc_mul(uint32_t P, uint32_t Rinv, const uint32_t* a, const uint32_t* b, uint32_t* out, size_t n);
 void orc_muladd(uint32_t P, uint32_t Rinv, const uint32_t* a, const uint32_t* b, const uint32_t* c, uint32_t* out,
                 size_t n);
 void orc_polymul_schoolbook(uint32_t P, const uint32_t* a, uint32_t da, const uint32_t* b, uint32_t db, uint32_t* c);
@@ -155,6 +158,74 @@ static int device_checks(void) {
   HIP_OK(hipStreamSynchronize(s));
   orc64_mul(Q, r64[3], xa, xb, xw, m);
   check(memcmp(xo, xw, 8 * m) == 0, "mont64_mul matches the oracle");
+
+  /* vector batches: 3 vectors (descriptors passed in the launch), then 20
+   * (descriptors uploaded), each a prefix of its own 4000-word segment */
+  mont_batch* vb = NULL;
+  check(mont_batch_reserve(20, &vb) == MONT_OK, "mont_batch_reserve");
+  for (int round = 0; round < 2; round++) {
+    const int cnt = round == 0 ? 3 : 20;
+    const size_t seg = 4000;
+    mont_vec_desc vd[20];
+    for (int i = 0; i < cnt; i++) {
+      vd[i].a = da + i * seg;
+      vd[i].b = db + i * seg;
+      vd[i].out = dout + i * seg;
+      vd[i].n = 1 + next64() % seg;
+      vd[i].P = p.P;
+      vd[i].Pprime = p.Pprime;
+    }
+    ok = mont_batch_update(vb, vd, cnt, s) == MONT_OK && mont_batch_mul(vb, s) == MONT_OK;
+    HIP_OK(hipMemcpyAsync(hout, dout, 4 * n, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int i = 0; i < cnt && ok; i++) {
+      orc_mul(P, ref[3], ha + i * seg, hb + i * seg, want, vd[i].n);
+      ok = memcmp(hout + i * seg, want, 4 * vd[i].n) == 0;
+    }
+    check(ok, round == 0 ? "mont_batch_mul, 3 vectors (descriptors in the launch)"
+                         : "mont_batch_mul, 20 vectors (descriptors uploaded)");
+  }
+  check(mont_batch_destroy(vb) == MONT_OK, "mont_batch_destroy");
+
+  /* a reusable plan: 2 products (lists passed in the launch), then 6 (lists
+   * uploaded); operands and results packed in one input and one output buffer */
+  ntt_ctx* c2 = NULL;
+  ntt_plan* pl = NULL;
+  void* dscr = NULL;
+  const size_t scr_cap = 1 << 20;
+  check(ntt_ctx_create(pr, 1, 16, &c2) == MONT_OK && ntt_plan_reserve(c2, 8, 4096, &pl) == MONT_OK,
+        "ntt_plan_reserve");
+  HIP_OK(hipMalloc(&dscr, scr_cap));
+  for (int round = 0; round < 2; round++) {
+    const int cnt = round == 0 ? 2 : 6;
+    polymul_desc pd[6];
+    uint64_t cpos = 0;
+    for (int i = 0; i < cnt; i++) {
+      pd[i].prime_id = 0;
+      pd[i].da = (uint32_t)(next64() % 2000);
+      pd[i].db = (uint32_t)(next64() % 2000);
+      pd[i].reserved = 0;
+      pd[i].a_off = (uint64_t)i * 5000;
+      pd[i].b_off = (uint64_t)i * 5000 + 2500;
+      pd[i].c_off = cpos;
+      cpos += pd[i].da + pd[i].db + 1;
+    }
+    size_t sb = 0;
+    ok = ntt_plan_update(pl, pd, cnt, 0, s) == MONT_OK && ntt_plan_info(pl, &sb, NULL, NULL, NULL, NULL) == MONT_OK &&
+         sb <= scr_cap && ntt_plan_execute(pl, da, dout, dscr, sb, 0, 0, s) == MONT_OK &&
+         ntt_plan_status(pl, dscr, s) == MONT_OK;
+    HIP_OK(hipMemcpyAsync(hout, dout, 4 * cpos, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int i = 0; i < cnt && ok; i++) {
+      orc_polymul_schoolbook(P, ha + pd[i].a_off, pd[i].da, ha + pd[i].b_off, pd[i].db, want);
+      ok = memcmp(hout + pd[i].c_off, want, 4 * (pd[i].da + pd[i].db + 1)) == 0;
+    }
+    check(ok, round == 0 ? "ntt_plan_execute, 2 products (lists in the launch)"
+                         : "ntt_plan_execute, 6 products (lists uploaded)");
+  }
+  check(ntt_plan_destroy(pl) == MONT_OK, "ntt_plan_destroy");
+  ntt_ctx_destroy(c2);
+  HIP_OK(hipFree(dscr));
 
   HIP_OK(hipFree(ya));
   HIP_OK(hipFree(yb));
