@@ -38,7 +38,8 @@ typedef struct ntt_ctx ntt_ctx;
  * each with L = min(log2_nmax, v2(P-1))), generated on the device by REDC
  * products of repeated squares.  Allocates device memory (8 * 2^L bytes per
  * prime) and synchronizes the device.  primes: host array of nprimes
- * (1..64) odd primes < 2^31.  log2_nmax in [1, 27].  The context is
+ * (1..64) odd primes < 2^31.  log2_nmax in [1, 23] (transforms up to 2^23;
+ * MONT_EINVAL above).  The context is
  * read-only afterwards and may be shared by streams and threads.
  * Errors: MONT_EINVAL (bad prime or argument), MONT_ENOMEM, MONT_EHIP.
  */
@@ -179,8 +180,66 @@ MONT_API mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_in
  * completed (MONT_OK) or timed out in a dependency wait (MONT_ETIMEOUT). */
 MONT_API mont_status ntt_plan_status(const ntt_plan* plan, const void* d_scratch, void* stream);
 
+/*
+ * ntt_plan_status_async -- enqueues on `stream` a copy of the status word of
+ * the last execution on d_scratch into the host word *h_status, without
+ * waiting: once the stream has passed this point, *h_status is 0 (the
+ * execution completed) or nonzero (a dependency wait gave up, as
+ * MONT_ETIMEOUT from ntt_plan_status).  Enqueue it after ntt_plan_execute on
+ * the same stream.  h_status should be pinned host memory (hipHostMalloc);
+ * the caller owns it and must not read it before the stream has passed the
+ * copy.  A plan with no products writes 0 at once.  Errors: MONT_EINVAL,
+ * MONT_EHIP.
+ */
+MONT_API mont_status ntt_plan_status_async(const ntt_plan* plan, const void* d_scratch, uint32_t* h_status,
+                                           void* stream);
+
 /* Frees the plan's device memory (synchronizes the device first). */
 MONT_API mont_status ntt_plan_destroy(ntt_plan* plan);
+
+/*
+ * One-call batches: the batch of uneven products, each with its own prime,
+ * in ONE call whose descriptors live in DEVICE memory.  A planning kernel
+ * (one workgroup) turns d_descs into the records and the task list a plan
+ * holds, inside d_scratch: the same split rule as ntt_plan_create and its
+ * phase task order (forward column tiles, half the single tasks, row
+ * blocks, the other half, inverse column tiles, each phase longest first,
+ * products of one length in index order).  Then one persistent launch runs
+ * every task and, for split products, one fix-up launch follows.  The call
+ * performs no host-device copy and no allocation, so it can be captured in a
+ * HIP graph, and every replay plans whatever descriptors d_descs then holds
+ * (the same count).  Each product's result equals ntt_polymul's.
+ *
+ * ntt_scratch_bytes -- bytes of d_scratch that ntt_polymul_batch needs for
+ * these `count` descriptors (a HOST array here, with the values the device
+ * copy will hold): a header, per-product records and counters, the task
+ * list, 2N words for each product of N > 2^13 after splitting, and the
+ * outputs of top parts.  Returns 0 if ctx is NULL or a descriptor is invalid
+ * (prime_id out of range, reserved != 0, da+db+1 > 2^31, N above the prime's
+ * table).  Pure host arithmetic, for admission by footprint.
+ *
+ * ntt_polymul_batch -- d_descs: `count` polymul_desc records in device
+ * memory (8-byte aligned); operands and outputs at the offsets they give in
+ * d_in and d_out (words; the caller guarantees they lie inside the buffers
+ * and that outputs do not overlap inputs or each other); d_scratch:
+ * scratch_bytes bytes, 16-byte aligned, caller-owned.  Host checks: NULL
+ * pointers, alignment, count < 0 (MONT_EINVAL) and scratch_bytes below the
+ * fixed part of the layout (MONT_ENOMEM).  Errors only the descriptors show
+ * (invalid descriptor, or scratch smaller than ntt_scratch_bytes) are found
+ * by the planning kernel: it records them in the scratch header and no
+ * product is computed; ntt_batch_status reports them.  Asynchronous on
+ * `stream`; calls sharing a scratch buffer must not overlap.
+ *
+ * ntt_batch_status -- synchronizes `stream` and returns the outcome of the
+ * last ntt_polymul_batch on d_scratch: MONT_OK, MONT_ETIMEOUT (a dependency
+ * wait gave up), or the planning error (MONT_EINVAL, MONT_ERANGE,
+ * MONT_ENOROOT, MONT_ENOMEM).
+ */
+MONT_API size_t ntt_scratch_bytes(const ntt_ctx* ctx, const polymul_desc* descs, int count);
+MONT_API mont_status ntt_polymul_batch(const ntt_ctx* ctx, const polymul_desc* d_descs, int count,
+                                       const uint32_t* d_in, uint32_t* d_out, void* d_scratch, size_t scratch_bytes,
+                                       void* stream);
+MONT_API mont_status ntt_batch_status(const void* d_scratch, void* stream);
 
 /*
  * Launch-shape tuning of the transform kernels (used by the autotuner):

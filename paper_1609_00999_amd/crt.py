@@ -158,18 +158,30 @@ class Batch:
                 torch.empty(max(1, 3 * self.out_words), dtype=torch.int32, device=device),
                 self.plan.alloc_scratch(device))
 
-    def run(self, coeffs, out, work, grid: int = 0):
+    def run(self, coeffs, out, work, grid: int = 0, check: bool = True, spin_limit: int = 0):
         """coeffs: device uint32 input (at least in_words before padding);
-        out: (out_words, 3) limbs; work: from buffers()."""
+        out: (out_words, 3) limbs; work: from buffers().  With check (the
+        default) the call synchronizes and raises MontError(MONT_ETIMEOUT)
+        when a dependency wait of the modular products' launch gave up;
+        without it the run stays asynchronous and status(work) tells."""
         red, prod, scratch = work
         n = coeffs.numel()
         if n > self.in_words:
             raise ValueError("input longer than planned")
         iw, ow = self.in_words, self.out_words
         reduce(self.prm, coeffs, out=red[:3 * iw].view(3, iw)[:, :n])
-        self.plan.execute(red, prod, scratch, grid=grid)
+        self.plan.execute(red, prod, scratch, grid=grid, spin_limit=spin_limit)
         combine(self.prm, prod[:ow], prod[ow:2 * ow], prod[2 * ow:3 * ow], out=out)
+        if check:
+            st = self.status(work)
+            if st != 0:
+                raise mont.MontError(st, "crt Batch.run: modular products")
         return out
+
+    def status(self, work) -> int:
+        """0 if the last run on these work buffers completed, else
+        MONT_ETIMEOUT (-6).  Synchronizes the current stream."""
+        return self.plan.status(work[2])
 
     def close(self):
         self.plan.close()

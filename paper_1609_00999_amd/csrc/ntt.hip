@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -43,7 +44,10 @@ namespace mont {
 
 constexpr int kRowLog = 13;            // row block = small-product limit: 2^13 residues
 constexpr int kLdsWords = 1 << 14;     // 64 KiB of LDS per workgroup
-constexpr int kMaxLog = 27;
+// Longest transform: 2^23.  Every multi-pass length 2^14 .. 2^23 has
+// compile-time column rounds; longer column tiles would hold fewer than eight
+// adjacent columns (2^(27-n) of them), whose strided rows read HBM poorly.
+constexpr int kMaxLog = 23;
 
 // Per-prime device constants.
 struct PrimeDev {
@@ -91,6 +95,131 @@ enum TaskKind : uint32_t { T_SMALL = 0, T_COLF_A = 1, T_COLF_B = 2, T_ROW = 3, T
 // Scratch header used by the persistent kernel (words).
 constexpr int kHdrWords = 64;          // [0] queue head, [1] status
 constexpr uint32_t kStatusTimeout = 1;
+// A batch planned on the device (ntt_polymul_batch) also keeps in its header
+// the task count, the fix-up chunk count, a planning error (a negative
+// mont_status, 0 if none) and the scratch words the plan needs (64-bit).
+constexpr int kHdrNtasks = 2, kHdrNchunks = 3, kHdrError = 4, kHdrWordsNeeded = 6;
+constexpr uint32_t kStatusPlanError = 2;
+
+// ---------------------------------------------------------------------------
+// Product shapes, shared by the host planner and the device planner.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ inline int ceil_log2(uint64_t x) {
+  int n = 0;
+  while (((uint64_t)1 << n) < x) n++;
+  return n;
+}
+
+// Column-tile width for a multi-pass length 2^n: as many adjacent columns as
+// fit 2^14 residues of LDS, at most the 2^13 columns there are.
+__host__ __device__ inline int col_lc(int n) { return 14 - (n - kRowLog) < kRowLog ? 14 - (n - kRowLog) : kRowLog; }
+
+// Splitting a product whose length L = da + db + 1 is just above h = N/2.
+// With both operands shorter than h, the cyclic product of length h gives
+// c_k + c_(h+k), and the top m = L - h coefficients of a and b (a[h-db ..
+// da], b[h-da .. db]) have a product whose coefficients m-1 .. 2m-2 are
+// c_h .. c_(L-1).  The split is taken when the top product's length 2^nt
+// (>= 2m - 1) is at most N/4: the pair then costs at most 3/4 of the
+// butterflies of the length-N product.  (With 2^nt = N/2 it would save only
+// one stage in log2 N, not worth a second product and the fix-up.)  Only
+// multi-pass products are split: a product of length <= 2^13 is one task
+// whose cost is mostly its fixed overhead.
+__host__ __device__ inline bool split_rule(uint32_t da, uint32_t db, int n, uint32_t& m, int& nt) {
+  if (n <= kRowLog) return false;
+  const uint64_t h = 1ull << (n - 1);
+  if ((uint64_t)da + 1 > h || (uint64_t)db + 1 > h) return false;
+  m = (uint32_t)((uint64_t)da + db + 1 - h);
+  nt = ceil_log2(2ull * m - 1);
+  return nt <= n - 2;
+}
+
+__host__ __device__ inline uint32_t product_tasks(int n) {
+  if (n <= kRowLog) return 1;
+  const uint32_t ntiles = 1u << (kRowLog - col_lc(n));
+  return 3 * ntiles + (1u << (n - kRowLog));
+}
+
+// One internal product ("slot") of a one-call batch: slot 2i is product i,
+// or its cyclic part when the split rule takes it; slot 2i + 1 is the top
+// part of a split product and unused otherwise.
+struct SlotShape {
+  int err;                  // nonzero: the product's descriptor is invalid (a mont_status)
+  bool used;
+  bool split;               // the product is split (both slots describe it)
+  int n;                    // log2 of the slot's transform length
+  uint32_t da, db;          // the slot's operand degrees
+  uint64_t a_off, b_off;    // the slot's operand offsets in the input
+  uint32_t nout;            // coefficients the slot stores
+  uint32_t m, h;            // split products: top coefficients and half length
+};
+
+__host__ __device__ inline SlotShape slot_shape(const polymul_desc& d, int part, uint32_t nprimes,
+                                                const uint32_t* logmax) {
+  SlotShape sh = {};
+  if (d.prime_id >= nprimes || d.reserved != 0) {
+    sh.err = MONT_EINVAL;
+    return sh;
+  }
+  const uint64_t L = (uint64_t)d.da + d.db + 1;
+  if (L > ((uint64_t)1 << 31)) {
+    sh.err = MONT_ERANGE;
+    return sh;
+  }
+  const int n = ceil_log2(L);
+  if ((uint32_t)n > logmax[d.prime_id]) {
+    sh.err = MONT_ENOROOT;
+    return sh;
+  }
+  uint32_t m = 0;
+  int nt = 0;
+  sh.split = split_rule(d.da, d.db, n, m, nt);
+  if (!sh.split) {
+    sh.used = part == 0;
+    sh.n = n;
+    sh.da = d.da;
+    sh.db = d.db;
+    sh.a_off = d.a_off;
+    sh.b_off = d.b_off;
+    sh.nout = (uint32_t)L;
+    return sh;
+  }
+  const uint32_t h = 1u << (n - 1);
+  sh.used = true;
+  sh.m = m;
+  sh.h = h;
+  if (part == 0) {              // cyclic part of length h, straight into the output
+    sh.n = n - 1;
+    sh.da = d.da;
+    sh.db = d.db;
+    sh.a_off = d.a_off;
+    sh.b_off = d.b_off;
+    sh.nout = h;
+  } else {                      // top part, into scratch
+    sh.n = nt;
+    sh.da = m - 1;
+    sh.db = m - 1;
+    sh.a_off = d.a_off + (h - d.db);
+    sh.b_off = d.b_off + (h - d.da);
+    sh.nout = 2 * m - 1;
+  }
+  return sh;
+}
+
+// Scratch words a slot's data take: the two length-N transforms of a
+// multi-pass product, then a top part's output (16-byte aligned).
+__host__ __device__ inline uint64_t slot_words(const SlotShape& sh, int part) {
+  if (!sh.used) return 0;
+  uint64_t w = sh.n > kRowLog ? (2ull << sh.n) : 0;
+  if (sh.split && part == 1) w += (sh.nout + 3u) & ~3u;
+  return w;
+}
+
+// Fix-up chunks of a product, counted on its top slot.
+__host__ __device__ inline uint32_t slot_chunks(const SlotShape& sh, int part) {
+  return sh.split && part == 1 ? (sh.m + kFixChunk - 1) / kFixChunk : 0u;
+}
+
 
 namespace {
 
@@ -599,17 +728,13 @@ __device__ __forceinline__ bool col_fixed(int n, uint32_t* X, uint32_t colbase, 
   }
 }
 
-// Column stages on an LDS tile for the other lengths: compile-time rounds
-// for 2^14, run-time rounds otherwise.
+// Column stages on an LDS tile for the one length col_fixed leaves out,
+// 2^14 (two rows of 2^13): compile-time rounds.  Contexts cap transforms at
+// 2^kMaxLog = 2^23, so no other length reaches this point.
 template <int NT, int RM, bool INV>
-__device__ __forceinline__ void col_stages(int n, int lc, uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
-  if (n == 14) {
-    if constexpr (INV) col_dit_fixed<NT, RM, 14, false, false>(X, colbase, tw, md);
-    else col_dif_fixed<NT, RM, 14, false, false>(X, colbase, tw, md);
-    return;
-  }
-  if constexpr (INV) lds_dit<NT, RM>(X, n - kRowLog, lc, kRowLog, colbase, tw, md);
-  else lds_dif<NT, 1, RM>(X, 0, n - kRowLog, lc, kRowLog, colbase, tw, md);
+__device__ __forceinline__ void col_stages(uint32_t* X, uint32_t colbase, const uint32_t* tw, Mod md) {
+  if constexpr (INV) col_dit_fixed<NT, RM, 14, false, false>(X, colbase, tw, md);
+  else col_dif_fixed<NT, RM, 14, false, false>(X, colbase, tw, md);
 }
 
 
@@ -686,7 +811,7 @@ __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, 
     }
   }
   __syncthreads();
-  col_stages<NT, RM, false>(n, lc, X, colbase, pr.twf, md);
+  col_stages<NT, RM, false>(X, colbase, pr.twf, md);
   for (uint32_t e = task_tid(); e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     st_out<COH>(dst + i, X[lds_at(e)]);
@@ -723,7 +848,7 @@ __device__ __forceinline__ void exec_col_dit(const PrimeDev& pr, int n, int lc, 
     }
   }
   __syncthreads();
-  col_stages<NT, RM, true>(n, lc, X, colbase, pr.twi, md);
+  col_stages<NT, RM, true>(X, colbase, pr.twi, md);
   for (uint32_t e = task_tid(); e < cnt; e += NT) {
     const uint32_t i = colbase + (e & cmask) + ((e >> lc) << kRowLog);
     if (i < nout) dst[i] = X[lds_at(e)];
@@ -872,6 +997,7 @@ struct PlanArgs {
   uint32_t* scr;            // header, two counters per product, then product scratch
   uint32_t spin_limit;
   uint32_t inl;             // 1: products and tasks are the copies below, not prods / tasks
+  uint32_t dyn;             // 1: planned on the device; the task count is in the scratch header
   ProdDev inl_prods[kInlineProds];
   uint2 inl_tasks[kInlineTasks];
 };
@@ -908,13 +1034,15 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
   uint32_t* cnt_col = g.scr + kHdrWords;
   uint32_t* cnt_row = cnt_col + g.nprods;
   const uint32_t S = 1u << kRowLog;
+  // written by the planning kernel before this launch (zero after a planning error)
+  const uint32_t ntasks = g.dyn ? g.scr[kHdrNtasks] : g.ntasks;
   for (;;) {
     if (threadIdx.x == 0) s_task = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     // uniform across the workgroup: keeps the task's fields and pointers in
     // scalar registers
     const uint32_t ti = __builtin_amdgcn_readfirstlane(s_task);
-    if (ti >= g.ntasks) break;
+    if (ti >= ntasks) break;
     const uint2 tk = g.inl ? g.inl_tasks[ti] : g.tasks[ti];
     const uint32_t p = tk.x;
     const uint32_t kind = tk.y >> 28;
@@ -965,8 +1093,12 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
 // device (a workgroup takes chunks; the fix-up of a chunk is found by binary
 // search on the chunks' first indices).  The cyclic part left c[k] = c_k +
 // c_(h+k); the top product t gives c_(h+k) = t[m-1+k].
+// A batch planned on the device passes dyn_nchunks, its header word holding
+// the chunk count (its records of unsplit products have m = 0 and are never
+// selected: each shares its first chunk index with a later record).
 __global__ __launch_bounds__(256) void k_split_fix(const FixDev* fx, uint32_t nfix, uint32_t nchunks, uint32_t* out,
-                                                   const uint32_t* scr) {
+                                                   const uint32_t* scr, const uint32_t* dyn_nchunks) {
+  if (dyn_nchunks) nchunks = *dyn_nchunks;
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
     uint32_t lo = 0, hi = nfix;                  // fx[lo].chunk0 <= c < fx[hi].chunk0
     while (hi - lo > 1) {
@@ -991,6 +1123,253 @@ __global__ __launch_bounds__(256) void k_split_fix(const FixDev* fx, uint32_t nf
 // sequence can be captured in a graph).
 __global__ void k_fill_zero(uint32_t* p, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Batch planning on the device (ntt_polymul_batch).  The descriptors are in
+// device memory; one workgroup turns them into the same records the host
+// planner makes (products, fix-ups, phase-ordered tasks) inside the caller's
+// scratch, so one call needs no host round trip and no upload, and a
+// captured graph replays with whatever descriptors the buffer then holds.
+//
+// Scratch layout (words): header | 2 counters x 2 count slots | ProdDev x 2
+// count | FixDev x count | tasks | data (64-word aligned), where data holds,
+// slot by slot, the two length-N transforms of each multi-pass slot and the
+// output of each top part.  The task list is in phase order: forward column
+// tiles, the first half of the single-task slots, row blocks, the other
+// half, inverse column tiles, each phase longest transform first and slots
+// in index order within one length (the host planner's phase order).
+// ---------------------------------------------------------------------------
+
+constexpr int kPlanThreads = 512;
+constexpr int kPlanWaves = kPlanThreads / 64;
+constexpr int kPlanBuckets = kMaxLog + 1;
+
+struct BatchLayout {
+  uint64_t cnt, prods, fixes, tasks;   // word offsets
+};
+
+__host__ __device__ inline BatchLayout batch_layout(uint32_t count) {
+  BatchLayout l;
+  l.cnt = kHdrWords;
+  l.prods = (l.cnt + 4ull * count + 63) & ~63ull;
+  l.fixes = l.prods + (sizeof(ProdDev) / 4) * 2ull * count;
+  l.tasks = l.fixes + (sizeof(FixDev) / 4) * (uint64_t)count;
+  return l;
+}
+
+__host__ __device__ inline uint64_t batch_data_offset(const BatchLayout& l, uint64_t ntasks) {
+  return (l.tasks + 2 * ntasks + 63) & ~63ull;
+}
+
+// Exclusive prefix sum over the workgroup (every thread calls it); *total
+// receives the sum.  Waves scan with lane shuffles, then add the totals of
+// the waves before them.
+__device__ __forceinline__ uint64_t plan_scan(uint64_t v, uint64_t* s_wsum, uint64_t* total) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  uint64_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t y = __shfl_up(x, d, 64);
+    if (lane >= (uint32_t)d) x += y;
+  }
+  if (lane == 63) s_wsum[wave] = x;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+  for (int w = 0; w < kPlanWaves; w++) {
+    if (w < (int)wave) before += s_wsum[w];
+    all += s_wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* primes, uint32_t nprimes,
+                                                              const polymul_desc* descs, uint32_t count,
+                                                              uint32_t* scr, uint64_t scr_words) {
+  __shared__ uint32_t s_logmax[64];
+  __shared__ uint32_t s_cnt[kPlanBuckets];          // slots per transform length
+  __shared__ unsigned long long s_words, s_chunks;
+  __shared__ int s_err;
+  __shared__ uint32_t s_base[kPlanBuckets];         // first task of the length's slots in their phase
+  __shared__ uint32_t s_rowb[kPlanBuckets], s_colib[kPlanBuckets];   // same, row blocks and inverse tiles
+  __shared__ uint32_t s_run[kPlanBuckets];          // slots of the length placed so far
+  __shared__ uint32_t s_wc[kPlanWaves][kPlanBuckets];
+  __shared__ uint64_t s_wsum[kPlanWaves];
+  __shared__ uint32_t s_C, s_R, s_half;
+  __shared__ uint64_t s_data, s_chk;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u, wave = tid >> 6;
+  const uint32_t nslots = 2 * count;
+  for (uint32_t i = tid; i < 64; i += kPlanThreads) s_logmax[i] = i < nprimes ? primes[i].logmax : 0u;
+  if (tid < (uint32_t)kPlanBuckets) {
+    s_cnt[tid] = 0;
+    s_run[tid] = 0;
+  }
+  if (tid == 0) {
+    s_words = 0;
+    s_chunks = 0;
+    s_err = 0;
+  }
+  __syncthreads();
+  // Pass 1: validate, count slots per length, sum data words and chunks.
+  for (uint32_t base = 0; base < nslots; base += kPlanThreads) {
+    const uint32_t slot = base + tid;
+    if (slot < nslots) {
+      const int part = (int)(slot & 1u);
+      const SlotShape sh = slot_shape(descs[slot >> 1], part, nprimes, s_logmax);
+      if (sh.err) atomicCAS(&s_err, 0, sh.err);
+      else if (sh.used) {
+        atomicAdd(&s_cnt[sh.n], 1u);
+        atomicAdd(&s_words, (unsigned long long)slot_words(sh, part));
+        atomicAdd(&s_chunks, (unsigned long long)slot_chunks(sh, part));
+      }
+    }
+  }
+  __syncthreads();
+  const BatchLayout lay = batch_layout(count);
+  if (tid == 0) {
+    // task bases per length, longest first within each phase
+    uint32_t C = 0, S = 0, R = 0, I = 0;
+    for (int n = kMaxLog; n >= 0; n--) {
+      if (n > kRowLog) {
+        const uint32_t nt = 1u << (kRowLog - col_lc(n)), nb = 1u << (n - kRowLog);
+        s_base[n] = C;
+        s_rowb[n] = R;
+        s_colib[n] = I;
+        C += s_cnt[n] * 2 * nt;
+        R += s_cnt[n] * nb;
+        I += s_cnt[n] * nt;
+      } else {
+        s_base[n] = S;
+        S += s_cnt[n];
+      }
+    }
+    const uint32_t half = S / 2;
+    for (int n = kRowLog + 1; n <= kMaxLog; n++) {
+      // forward tiles, then (after half the single tasks) the rows, then
+      // (after the rest) the inverse tiles
+      s_rowb[n] += C + half;
+      s_colib[n] += C + S + R;
+    }
+    s_C = C;
+    s_R = R;
+    s_half = half;
+    const uint64_t ntasks = (uint64_t)C + S + R + I;
+    const uint64_t need = batch_data_offset(lay, ntasks) + s_words;
+    int err = s_err;
+    if (!err && need > scr_words) err = MONT_ENOMEM;
+    if (!err && ntasks > 0xFFFFFFFFull) err = MONT_ERANGE;
+    s_err = err;
+    scr[0] = 0;
+    scr[1] = err ? kStatusPlanError : 0u;
+    scr[kHdrNtasks] = err ? 0u : (uint32_t)ntasks;
+    scr[kHdrNchunks] = err ? 0u : (uint32_t)s_chunks;
+    scr[kHdrError] = (uint32_t)err;
+    scr[kHdrWordsNeeded] = (uint32_t)need;
+    scr[kHdrWordsNeeded + 1] = (uint32_t)(need >> 32);
+    s_data = batch_data_offset(lay, ntasks);
+    s_chk = 0;
+  }
+  __syncthreads();
+  if (s_err) return;                                 // uniform: every thread leaves
+  for (uint64_t i = tid; i < 4ull * count; i += kPlanThreads) scr[lay.cnt + i] = 0u;
+  ProdDev* prods = reinterpret_cast<ProdDev*>(scr + lay.prods);
+  FixDev* fixes = reinterpret_cast<FixDev*>(scr + lay.fixes);
+  uint2* tasks = reinterpret_cast<uint2*>(scr + lay.tasks);
+  const uint32_t C = s_C, R = s_R, half = s_half;
+  // Pass 2: ranks within each length (index order), data offsets and fix-up
+  // chunks by prefix sums, then the records and the tasks.
+  for (uint32_t base = 0; base < nslots; base += kPlanThreads) {
+    const uint32_t slot = base + tid;
+    const int part = (int)(slot & 1u);
+    SlotShape sh = {};
+    const polymul_desc d = slot < nslots ? descs[slot >> 1] : polymul_desc{};
+    if (slot < nslots) sh = slot_shape(d, part, nprimes, s_logmax);
+    const uint32_t b = sh.used ? (uint32_t)sh.n : 0xFFu;
+    uint32_t inwave = 0;
+#pragma nounroll
+    for (uint32_t k = 0; k < (uint32_t)kPlanBuckets; k++) {
+      const uint64_t mask = __ballot(b == k);
+      if (lane == 0) s_wc[wave][k] = (uint32_t)__popcll(mask);
+      if (b == k) inwave = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    }
+    uint64_t wtot = 0, ctot = 0;
+    const uint64_t woff = plan_scan(slot_words(sh, part), s_wsum, &wtot);    // barriers also publish s_wc
+    const uint64_t coff = plan_scan(slot < nslots && part == 1 ? slot_chunks(sh, part) : 0u, s_wsum, &ctot);
+    if (slot < nslots) {
+      uint32_t rank = 0;
+      if (sh.used) {
+        rank = s_run[b] + inwave;
+        for (uint32_t w = 0; w < wave; w++) rank += s_wc[w][b];
+      }
+      const uint64_t dat = s_data + woff;
+      const uint32_t chunk0 = (uint32_t)(s_chk + coff);
+      if (sh.used) {
+        ProdDev pd = {};
+        pd.prime_id = d.prime_id;
+        pd.n = (uint32_t)sh.n;
+        pd.da = sh.da;
+        pd.db = sh.db;
+        pd.a_off = sh.a_off;
+        pd.b_off = sh.b_off;
+        pd.nout = sh.nout;
+        pd.to_scr = sh.split && part == 1 ? 1u : 0u;
+        pd.c_off = pd.to_scr ? dat + (sh.n > kRowLog ? (2ull << sh.n) : 0ull) : d.c_off;
+        uint32_t nt = 0, nb = 0;
+        if (sh.n > kRowLog) {
+          pd.lc = (uint32_t)col_lc(sh.n);
+          nt = pd.ntiles = 1u << (kRowLog - pd.lc);
+          nb = pd.nblocks = 1u << (sh.n - kRowLog);
+          pd.scr_off = dat;
+        }
+        prods[slot] = pd;
+        if (sh.n <= kRowLog) {
+          const uint32_t q = s_base[b] + rank;
+          const uint32_t at = q < half ? C + q : C + R + q;
+          tasks[at] = make_uint2(slot, (uint32_t)T_SMALL << 28);
+        } else {
+          const uint32_t f0 = s_base[b] + rank * 2 * nt, r0 = s_rowb[b] + rank * nb, i0 = s_colib[b] + rank * nt;
+#pragma nounroll
+          for (uint32_t t = 0; t < nt; t++) {
+            tasks[f0 + t] = make_uint2(slot, ((uint32_t)T_COLF_A << 28) | t);
+            tasks[f0 + nt + t] = make_uint2(slot, ((uint32_t)T_COLF_B << 28) | t);
+            tasks[i0 + t] = make_uint2(slot, ((uint32_t)T_COLI << 28) | t);
+          }
+#pragma nounroll
+          for (uint32_t j = 0; j < nb; j++) tasks[r0 + j] = make_uint2(slot, ((uint32_t)T_ROW << 28) | j);
+        }
+      }
+      // one fix-up record per product: the top slot writes a split product's,
+      // slot 2i an unsplit one's (m = 0, never selected)
+      if (sh.split && part == 1) {
+        FixDev f;
+        f.c_off = d.c_off;
+        f.t_off = dat + (sh.n > kRowLog ? (2ull << sh.n) : 0ull);
+        f.m = sh.m;
+        f.h = sh.h;
+        f.P = primes[d.prime_id].P;
+        f.chunk0 = chunk0;
+        fixes[slot >> 1] = f;
+      } else if (!sh.split && part == 0) {
+        FixDev f = {};
+        f.chunk0 = chunk0;
+        fixes[slot >> 1] = f;
+      }
+    }
+    __syncthreads();
+    if (tid < (uint32_t)kPlanBuckets) {
+      uint32_t add = 0;
+      for (int w = 0; w < kPlanWaves; w++) add += s_wc[w][tid];
+      s_run[tid] += add;
+    }
+    if (tid == 0) {
+      s_data += wtot;
+      s_chk += ctot;
+    }
+    __syncthreads();
+  }
 }
 
 // Twiddle generation.  pw[b] = residue of w^(2^b) by repeated squaring of
@@ -1074,15 +1453,6 @@ bool is_prime_host(uint32_t P) {
   return true;
 }
 
-int ceil_log2(uint64_t x) {
-  int n = 0;
-  while (((uint64_t)1 << n) < x) n++;
-  return n;
-}
-
-// Column-tile width for a multi-pass length 2^n: as many adjacent columns as
-// fit 2^14 residues of LDS, at most the 2^13 columns there are.
-int col_lc(int n) { return std::min(kRowLog, 14 - (n - kRowLog)); }
 
 }  // namespace
 
@@ -1429,31 +1799,6 @@ extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint3
 // ---------------------------------------------------------------------------
 
 namespace {
-
-// Splitting a product whose length L = da + db + 1 is just above h = N/2.
-// With both operands shorter than h, the cyclic product of length h gives
-// c_k + c_(h+k), and the top m = L - h coefficients of a and b (a[h-db ..
-// da], b[h-da .. db]) have a product whose coefficients m-1 .. 2m-2 are
-// c_h .. c_(L-1).  The split is taken when the top product's length 2^nt
-// (>= 2m - 1) is at most N/4: the pair then costs at most 3/4 of the
-// butterflies of the length-N product.  (With 2^nt = N/2 it would save only
-// one stage in log2 N, not worth a second product and the fix-up.)  Only
-// multi-pass products are split: a product of length <= 2^13 is one task
-// whose cost is mostly its fixed overhead.
-bool split_rule(uint32_t da, uint32_t db, int n, uint32_t& m, int& nt) {
-  if (n <= kRowLog) return false;
-  const uint64_t h = 1ull << (n - 1);
-  if ((uint64_t)da + 1 > h || (uint64_t)db + 1 > h) return false;
-  m = (uint32_t)((uint64_t)da + db + 1 - h);
-  nt = ceil_log2(2ull * m - 1);
-  return nt <= n - 2;
-}
-
-uint32_t product_tasks(int n) {
-  if (n <= kRowLog) return 1;
-  const uint32_t ntiles = 1u << (kRowLog - col_lc(n));
-  return 3 * ntiles + (1u << (n - kRowLog));
-}
 
 // Groups of multi-pass products in the task pipeline of a plan.
 constexpr int kPipeGroups = 8;
@@ -1838,6 +2183,9 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   uint32_t nz = (uint32_t)(kHdrWords + 2ull * plan->count);
   hipLaunchKernelGGL(k_fill_zero, dim3(std::min(1024u, (nz + 255) / 256)), dim3(256), 0, s, scr, nz);
   PlanArgs g;
+  // every scalar field zero (the inline arrays that follow are filled below
+  // only as far as they are used)
+  std::memset(&g, 0, offsetof(PlanArgs, inl_prods));
   g.primes = plan->ctx->d_primes;
   g.prods = plan->d_prods;
   g.tasks = plan->d_tasks;
@@ -1857,7 +2205,7 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   launch_persistent(g, gsz, s);
   if (plan->nfix > 0)
     hipLaunchKernelGGL(k_split_fix, dim3(std::min(plan->nchunks, 8192u)), dim3(256), 0, s, plan->d_fix, plan->nfix,
-                       plan->nchunks, d_out, static_cast<const uint32_t*>(scr));
+                       plan->nchunks, d_out, static_cast<const uint32_t*>(scr), nullptr);
   return last_launch_status();
 }
 
@@ -1870,6 +2218,78 @@ extern "C" mont_status ntt_plan_status(const ntt_plan* plan, const void* d_scrat
     return MONT_EHIP;
   if (hipStreamSynchronize(s) != hipSuccess) return MONT_EHIP;
   return st == 0 ? MONT_OK : MONT_ETIMEOUT;
+}
+
+extern "C" mont_status ntt_plan_status_async(const ntt_plan* plan, const void* d_scratch, uint32_t* h_status,
+                                             void* stream) {
+  if (!plan || !d_scratch || !h_status) return MONT_EINVAL;
+  if (plan->count == 0) {
+    *h_status = 0;
+    return MONT_OK;
+  }
+  if (hipMemcpyAsync(h_status, static_cast<const uint32_t*>(d_scratch) + 1, 4, hipMemcpyDeviceToHost,
+                     as_stream(stream)) != hipSuccess)
+    return MONT_EHIP;
+  return MONT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One-call batches planned on the device.
+// ---------------------------------------------------------------------------
+
+extern "C" size_t ntt_scratch_bytes(const ntt_ctx* ctx, const polymul_desc* descs, int count) {
+  if (!ctx || count < 0 || (count > 0 && !descs)) return 0;
+  const uint32_t np = (uint32_t)ctx->params.size();
+  uint64_t ntasks = 0, words = 0;
+  for (int i = 0; i < count; i++)
+    for (int part = 0; part < 2; part++) {
+      const SlotShape sh = slot_shape(descs[i], part, np, ctx->logmax.data());
+      if (sh.err) return 0;
+      if (!sh.used) continue;
+      ntasks += product_tasks(sh.n);
+      words += slot_words(sh, part);
+    }
+  return (size_t)(batch_data_offset(batch_layout((uint32_t)count), ntasks) + words) * 4;
+}
+
+extern "C" mont_status ntt_polymul_batch(const ntt_ctx* ctx, const polymul_desc* d_descs, int count,
+                                         const uint32_t* d_in, uint32_t* d_out, void* d_scratch, size_t scratch_bytes,
+                                         void* stream) {
+  if (!ctx || count < 0 || !d_scratch || (count > 0 && (!d_descs || !d_in || !d_out))) return MONT_EINVAL;
+  if (!aligned16(d_scratch) || ((uintptr_t)d_descs & 7u) != 0) return MONT_EINVAL;
+  const BatchLayout lay = batch_layout((uint32_t)count);
+  if (scratch_bytes / 4 < batch_data_offset(lay, 0)) return MONT_ENOMEM;
+  hipStream_t s = as_stream(stream);
+  (void)hipGetLastError();
+  uint32_t* scr = static_cast<uint32_t*>(d_scratch);
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, ctx->d_primes, (uint32_t)ctx->params.size(),
+                     d_descs, (uint32_t)count, scr, (uint64_t)(scratch_bytes / 4));
+  if (count == 0) return last_launch_status();
+  PlanArgs g;
+  std::memset(&g, 0, sizeof(g));
+  g.primes = ctx->d_primes;
+  g.prods = reinterpret_cast<const ProdDev*>(scr + lay.prods);
+  g.tasks = reinterpret_cast<const uint2*>(scr + lay.tasks);
+  g.nprods = 2u * (uint32_t)count;
+  g.in = d_in;
+  g.out = d_out;
+  g.scr = scr;
+  g.spin_limit = 1u << 24;
+  g.dyn = 1;
+  launch_persistent(g, (uint32_t)persistent_grid(), s);
+  hipLaunchKernelGGL(k_split_fix, dim3(1024), dim3(256), 0, s, reinterpret_cast<const FixDev*>(scr + lay.fixes),
+                     (uint32_t)count, 0u, d_out, static_cast<const uint32_t*>(scr), scr + kHdrNchunks);
+  return last_launch_status();
+}
+
+extern "C" mont_status ntt_batch_status(const void* d_scratch, void* stream) {
+  if (!d_scratch) return MONT_EINVAL;
+  hipStream_t s = as_stream(stream);
+  uint32_t hdr[8];
+  if (hipMemcpyAsync(hdr, d_scratch, sizeof(hdr), hipMemcpyDeviceToHost, s) != hipSuccess) return MONT_EHIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return MONT_EHIP;
+  if (hdr[kHdrError] != 0) return (mont_status)(int32_t)hdr[kHdrError];
+  return hdr[1] == 0 ? MONT_OK : MONT_ETIMEOUT;
 }
 
 extern "C" mont_status ntt_plan_destroy(ntt_plan* plan) {

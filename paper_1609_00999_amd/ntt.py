@@ -55,6 +55,11 @@ def register(L) -> None:
                                 ctypes.POINTER(c_u64), ctypes.POINTER(c_int)]
     L.ntt_plan_execute.argtypes = [c_vp, c_vp, c_vp, c_vp, c_size, c_int, c_u32, c_vp]
     L.ntt_plan_status.argtypes = [c_vp, c_vp, c_vp]
+    L.ntt_plan_status_async.argtypes = [c_vp, c_vp, c_vp, c_vp]
+    L.ntt_scratch_bytes.argtypes = [c_vp, c_vp, c_int]
+    L.ntt_scratch_bytes.restype = c_size
+    L.ntt_polymul_batch.argtypes = [c_vp, c_vp, c_int, c_vp, c_vp, c_vp, c_size, c_vp]
+    L.ntt_batch_status.argtypes = [c_vp, c_vp]
     L.ntt_plan_destroy.argtypes = [c_vp]
 
 
@@ -268,7 +273,57 @@ class Plan:
                                                mont.stream_handle(stream)), "ntt_plan_execute")
         return out
 
-    def status(self, scratch) -> int:
+    def status(self, scratch, stream=None) -> int:
         """0 if the last execution on this scratch completed, else MONT_ETIMEOUT (-6). Synchronizes."""
         return int(mont.lib().ntt_plan_status(self.handle, mont.dev_ptr(scratch, "scratch"),
-                                              mont.stream_handle()))
+                                              mont.stream_handle(stream)))
+
+    def status_async(self, scratch, host_word_ptr: int, stream=None) -> None:
+        """Enqueue a copy of the last execution's status word into the pinned
+        host word at host_word_ptr (0: completed, nonzero: a wait gave up)."""
+        mont.check(mont.lib().ntt_plan_status_async(self.handle, mont.dev_ptr(scratch, "scratch"), host_word_ptr,
+                                                    mont.stream_handle(stream)), "ntt_plan_status_async")
+
+
+# ---------------------------------------------------------------------------
+# One-call batches planned on the device (ntt_polymul_batch)
+# ---------------------------------------------------------------------------
+
+def batch_scratch_bytes(ctx: Context, descs: np.ndarray) -> int:
+    """Scratch bytes ntt_polymul_batch needs for these (host) descriptors;
+    raises ValueError if a descriptor is invalid for the context."""
+    descs = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+    n = int(mont.lib().ntt_scratch_bytes(ctx.handle, descs.ctypes.data if len(descs) else None, len(descs)))
+    if n == 0:
+        raise ValueError("invalid descriptor for this context")
+    return n
+
+
+def descs_to_device(descs: np.ndarray, device="cuda"):
+    """The descriptors as a device tensor (int32 words) for polymul_batch."""
+    torch = _torch()
+    descs = np.ascontiguousarray(descs, dtype=DESC_DTYPE)
+    words = descs.view(np.int32) if len(descs) else np.zeros(0, dtype=np.int32)
+    return torch.from_numpy(words.copy()).to(device)
+
+
+def polymul_batch(ctx: Context, d_descs, count: int, coeffs_in, out, scratch, stream=None):
+    """Every product of a batch in one call: the descriptors (device words,
+    count records) are planned on the device inside `scratch`, then one
+    persistent launch and the split-product fix-up run, all on `stream`."""
+    if d_descs.numel() * d_descs.element_size() < count * DESC_DTYPE.itemsize:
+        raise ValueError("descriptor buffer shorter than count records")
+    mont.check(mont.lib().ntt_polymul_batch(ctx.handle, mont.dev_ptr(d_descs, "descs") if count else None, count,
+                                            mont.dev_ptr(coeffs_in, "coeffs_in") if count else None,
+                                            mont.dev_ptr(out, "out") if count else None,
+                                            mont.dev_ptr(scratch, "scratch"),
+                                            scratch.numel() * scratch.element_size(), mont.stream_handle(stream)),
+               "ntt_polymul_batch")
+    return out
+
+
+def batch_status(scratch, stream=None) -> int:
+    """Status of the last ntt_polymul_batch on this scratch (synchronizes):
+    0, MONT_ETIMEOUT, or the planning error (MONT_EINVAL, MONT_ERANGE,
+    MONT_ENOROOT, MONT_ENOMEM)."""
+    return int(mont.lib().ntt_batch_status(mont.dev_ptr(scratch, "scratch"), mont.stream_handle(stream)))

@@ -235,9 +235,10 @@ class DeviceInputs:
         pos = 0
         for r in reqs:
             n = r.size if r.kind == "mul" else r.size + 1
-            offs[r.rid] = (pos, pos + n, n)
-            pos += 2 * n
-            pos = (pos + 3) & ~3            # keep every operand 16-byte aligned
+            # both operands start on a 16-byte boundary, so the kernels take
+            # their 128-bit paths for every request
+            offs[r.rid] = (pos, pos + _a4(n), n)
+            pos += 2 * _a4(n)
         self.arena = torch.empty(max(4, pos), dtype=torch.int32, device=device)
         self.offs = offs
         self.kinds = {r.rid: r.kind for r in reqs}
@@ -267,13 +268,20 @@ class GpuBatchExecutor:
     slot's stream."""
 
     def __init__(self, ctx, inputs: DeviceInputs, slots: int, max_batch: int, keep_results: bool = True,
-                 max_tasks: int = 1 << 20, arena_bytes: int = 1 << 30):
+                 max_tasks: int = 1 << 20, arena_bytes: int = 1 << 30, spin_limit: int = 0):
         import torch
         from . import mont, ntt
         self.torch, self.mont, self.ntt = torch, mont, ntt
         self.ctx = ctx
         self.inputs = inputs
         self.keep = keep_results
+        # bound on a transform task's dependency waits (0: the library default)
+        self.spin_limit = int(spin_limit)
+        # One pinned status word per slot: each batch's persistent launch
+        # copies its status there on the slot's stream before the batch's
+        # completion event, so finish() reads it without a synchronization.
+        self.status_host = torch.zeros(slots, dtype=torch.int32, pin_memory=True)
+        self._status_ptr = self.status_host.data_ptr()
         self.params = [mont.setup(P) for P in ctx.primes]
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.vecb = [mont.Batch(max_batch) for _ in range(slots)]
@@ -357,23 +365,33 @@ class GpuBatchExecutor:
         if polys:
             out = take(cpos)
             scr = take(scr_words)
-            plan.execute(self.inputs.arena, out, scr, stream=s)
+            plan.execute(self.inputs.arena, out, scr, spin_limit=self.spin_limit, stream=s)
+            plan.status_async(scr, self._status_ptr + 4 * slot, stream=s)
             keep += [out, scr]
             for i, j in enumerate(polys):
                 c0 = int(desc["c_off"][i])
                 j.result = out[c0:c0 + 2 * j.size + 1]
         ev = torch.cuda.Event()
         ev.record(s)
-        return (ev, batch, keep, slot, arena is not None)
+        return (ev, batch, keep, slot, arena is not None, bool(polys))
 
     def poll(self, handle) -> bool:
         return handle[0].query()
 
     def finish(self, handle) -> dict:
-        ev, batch, keep, slot, in_arena = handle
+        """Keeps or drops each result; returns {rid: error} for the requests
+        whose work failed on the device (a transform launch whose dependency
+        wait gave up fails every polynomial product of its batch)."""
+        ev, batch, keep, slot, in_arena, had_polys = handle
         torch = self.torch
+        errors = {}
+        if had_polys and int(self.status_host[slot]) != 0:
+            msg = "MONT_ETIMEOUT: a dependency wait of the batch's transform launch gave up"
+            for j in batch:
+                if j.kind == "polymul":
+                    errors[j.rid] = msg
         for j in batch:
-            if not _keeps(self.keep, j.rid):
+            if j.rid in errors or not _keeps(self.keep, j.rid):
                 j.result = None
             elif in_arena:
                 # The slot's next batch reuses the arena: copy on the slot's
@@ -381,7 +399,7 @@ class GpuBatchExecutor:
                 with torch.cuda.stream(self.streams[slot]):
                     dst = self.kept.get(j.rid)
                     j.result = dst.copy_(j.result) if dst is not None else j.result.clone()
-        return {}
+        return errors
 
     def close(self):
         for b in self.vecb:

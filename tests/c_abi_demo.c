@@ -71,6 +71,8 @@ static int host_checks(void) {
   check(mont_mul(&p, NULL, NULL, NULL, 0, NULL) == MONT_OK, "n = 0 enqueues nothing");
   check(ntt_polymul_scratch_bytes(100, 100) == 0 && ntt_polymul_scratch_bytes(10000, 10000) == ((size_t)8 << 15),
         "ntt_polymul_scratch_bytes");
+  check(ntt_scratch_bytes(NULL, NULL, 0) == 0, "ntt_scratch_bytes without a context");
+  check(ntt_polymul_batch(NULL, NULL, 0, NULL, NULL, NULL, 0, NULL) == MONT_EINVAL, "ntt_polymul_batch validation");
   return failures;
 }
 
@@ -224,6 +226,49 @@ static int device_checks(void) {
                          : "ntt_plan_execute, 6 products (lists uploaded)");
   }
   check(ntt_plan_destroy(pl) == MONT_OK, "ntt_plan_destroy");
+
+  /* a one-call batch: six products whose descriptors sit in device memory
+   * and are planned there; degrees 8200 x 8200 (length just above 2^14) take
+   * the split path and its fix-up */
+  {
+    const uint32_t degs[6][2] = {{8200, 8200}, {3000, 2000}, {1, 0}, {0, 0}, {9000, 7000}, {500, 1999}};
+    polymul_desc bd[6];
+    uint64_t apos = 0, cpos = 0;
+    for (int i = 0; i < 6; i++) {
+      bd[i].prime_id = 0;
+      bd[i].da = degs[i][0];
+      bd[i].db = degs[i][1];
+      bd[i].reserved = 0;
+      bd[i].a_off = apos;
+      apos += bd[i].da + 1;
+      bd[i].b_off = apos;
+      apos += bd[i].db + 1;
+      bd[i].c_off = cpos;
+      cpos += bd[i].da + bd[i].db + 1;
+    }
+    const size_t sb = ntt_scratch_bytes(c2, bd, 6);
+    check(sb > 0 && ntt_scratch_bytes(c2, bd, -1) == 0, "ntt_scratch_bytes");
+    void* bscr = NULL;
+    polymul_desc* ddesc = NULL;
+    HIP_OK(hipMalloc(&bscr, sb));
+    HIP_OK(hipMalloc((void**)&ddesc, sizeof(bd)));
+    HIP_OK(hipMemcpy(ddesc, bd, sizeof(bd), hipMemcpyHostToDevice));
+    ok = ntt_polymul_batch(c2, ddesc, 6, da, dout, bscr, sb, s) == MONT_OK && ntt_batch_status(bscr, s) == MONT_OK;
+    HIP_OK(hipMemcpyAsync(hout, dout, 4 * cpos, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int i = 0; i < 6 && ok; i++) {
+      orc_polymul_schoolbook(P, ha + bd[i].a_off, bd[i].da, ha + bd[i].b_off, bd[i].db, want);
+      ok = memcmp(hout + bd[i].c_off, want, 4 * (bd[i].da + bd[i].db + 1)) == 0;
+    }
+    check(ok, "ntt_polymul_batch, 6 products planned on the device");
+    check(ntt_polymul_batch(c2, ddesc, 6, da, dout, bscr, sb - 4, s) == MONT_OK &&
+              ntt_batch_status(bscr, s) == MONT_ENOMEM,
+          "scratch below ntt_scratch_bytes: MONT_ENOMEM from the planning kernel");
+    check(ntt_polymul_batch(c2, ddesc, 6, da, dout, bscr, 64, s) == MONT_ENOMEM,
+          "scratch below the fixed layout: MONT_ENOMEM on the host");
+    HIP_OK(hipFree(bscr));
+    HIP_OK(hipFree(ddesc));
+  }
   ntt_ctx_destroy(c2);
   HIP_OK(hipFree(dscr));
 

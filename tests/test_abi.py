@@ -104,6 +104,9 @@ def test_ntt_host_validation(L):
     assert L.ntt_ctx_create(arr, 0, 23, C.byref(h)) == -1
     assert L.ntt_ctx_create(arr, 1, 0, C.byref(h)) == -1
     assert L.ntt_ctx_create(arr, 1, 28, C.byref(h)) == -1
+    # transforms are capped at 2^23: a longer table is refused before any HIP call
+    for bad_log in (24, 25, 27):
+        assert L.ntt_ctx_create(arr, 1, bad_log, C.byref(h)) == -1
     assert L.ntt_ctx_create(None, 1, 23, C.byref(h)) == -1
     assert L.ntt_ctx_create(arr, 1, 23, None) == -1
     assert L.ntt_ctx_destroy(None) == -1

@@ -126,6 +126,30 @@ def test_batch_matches_single_and_oracle(env):
     cb.close()
 
 
+def test_batch_run_reports_a_timeout(env):
+    """A one-sleep wait limit on the modular products' launch: the waits of
+    long products give up (every kernel still exits), run() raises
+    MONT_ETIMEOUT, and the next run on the same buffers is exact."""
+    crt, _, ctx, prm = env
+    from paper_1609_00999_amd import mont
+    batch = wl.int_products(count=6, lo_log2=17, hi_log2=18, seed=12)
+    cb = crt.Batch.from_batch(ctx, prm, batch)
+    work = cb.buffers()
+    out = torch.empty((batch.out_len, 3), dtype=torch.int32, device="cuda")
+    din = dev(batch.coeffs)
+    with pytest.raises(mont.MontError) as ei:
+        cb.run(din, out, work, spin_limit=1)
+    assert ei.value.status == -6
+    cb.run(din, out, work)
+    assert cb.status(work) == 0
+    got = host(out).reshape(-1, 3)
+    for i in (0, batch.count - 1):
+        _, a, b = batch.operands(i)
+        c0 = int(batch.c_off[i])
+        assert np.array_equal(got[c0: c0 + a.size + b.size - 1], oracle_exact(a, b)), i
+    cb.close()
+
+
 def test_errors(env):
     crt, ntt, ctx, prm = env
     from paper_1609_00999_amd import mont

@@ -166,16 +166,15 @@ def test_bandwidth_config_full_size(M, pi):
 
 
 def test_pow_config(M):
-    """n = 2^24 bases, 31-bit exponents, P = 998244353: sampled parity with the
-    oracle, and Fermat a^(P-1) = 1 on the first 2^16 bases."""
+    """n = 2^24 bases, 31-bit exponents, P = 998244353: every power compared
+    with the oracle, and Fermat a^(P-1) = 1 on the first 2^16 bases."""
     P = wl.P_POW
     prm = M.setup(P)
     base, e = wl.pow_inputs()
     out = host(M.pow(prm, dev(base), dev(e)))
-    rng = np.random.default_rng(33)
-    idx = np.unique(np.concatenate([np.arange(4096), np.arange(base.size - 4096, base.size),
-                                    rng.integers(0, base.size, 1 << 18)]))
-    assert np.array_equal(out[idx], oracle.mont_pow(P, base[idx], e[idx]))
+    want = oracle.mont_pow(P, base, e)
+    bad = np.flatnonzero(out != want)
+    assert bad.size == 0, (bad.size, bad[:8].tolist())
     sub = base[: 1 << 16]
     f = host(M.pow(prm, dev(sub), dev(np.full(sub.size, P - 1, dtype=np.uint32))))
     assert np.all(f == prm.R1)

@@ -115,32 +115,30 @@ def test_argument_errors(M64):
 
 @pytest.mark.parametrize("pi", range(4))
 def test_bandwidth64_full_size(M64, pi):
-    """2^27 residues per array: mul and in-place mul-add, sampled against the
-    oracle (head, tail and 2^18 random positions)."""
+    """2^27 residues per array: mul and in-place mul-add, every element
+    compared with the oracle."""
     P, a, b, c = wl.bandwidth_triple64(pi)
     prm = M64.setup(P)
     da, db, dc = dev(a), dev(b), dev(c)
     got = host(M64.mul(prm, da, db))
-    rng = np.random.default_rng(pi)
-    idx = np.unique(np.concatenate([np.arange(4096), np.arange(a.size - 4096, a.size),
-                                    rng.integers(0, a.size, 1 << 18)]))
-    assert np.array_equal(got[idx], oracle.mont_mul64(P, a[idx], b[idx]))
+    bad = np.flatnonzero(got != oracle.mont_mul64(P, a, b))
+    assert bad.size == 0, (bad.size, bad[:8].tolist())
     del got
     M64.muladd(prm, da, db, dc, out=dc)
     got = host(dc)
-    assert np.array_equal(got[idx], oracle.mont_muladd64(P, a[idx], b[idx], c[idx]))
+    bad = np.flatnonzero(got != oracle.mont_muladd64(P, a, b, c))
+    assert bad.size == 0, (bad.size, bad[:8].tolist())
 
 
 def test_pow64_config(M64):
-    """2^22 bases and 64-bit exponents modulo 2^63 - 25: sampled parity and
-    Fermat on the first 2^14 bases."""
+    """2^22 bases and 64-bit exponents modulo 2^63 - 25: every power compared
+    with the oracle, and Fermat on the first 2^14 bases."""
     P = wl.PRIMES64[3]
     prm = M64.setup(P)
     base, e = wl.pow64_inputs()
     out = host(M64.pow(prm, dev(base), dev(e)))
-    rng = np.random.default_rng(4)
-    idx = np.unique(np.concatenate([np.arange(2048), rng.integers(0, base.size, 1 << 15)]))
-    assert np.array_equal(out[idx], oracle.mont_pow64(P, base[idx], e[idx]))
+    bad = np.flatnonzero(out != oracle.mont_pow64(P, base, e))
+    assert bad.size == 0, (bad.size, bad[:8].tolist())
     sub = base[: 1 << 14]
     f = host(M64.pow(prm, dev(sub), dev(np.full(sub.size, P - 1, dtype=np.uint64))))
     assert np.all(f == prm.R1)

@@ -146,7 +146,7 @@ def test_polymul_special_cases(N, ctx):
 @pytest.mark.parametrize("da,db", [((1 << 22) - 1, (1 << 22) - 1), (1500000, 1500000), ((1 << 21) - 1, 1 << 20)])
 def test_polymul_largest_length(N, ctx, da, db):
     """N = 2^23, the longest transform the tables support, and N = 2^22
-    (column tiles of 32 columns): Schwartz-Zippel."""
+    (column tiles of 32 columns): every coefficient against the oracle."""
     pid = 1
     P = PRIMES[pid]
     rng = np.random.default_rng(da + db)
@@ -154,8 +154,27 @@ def test_polymul_largest_length(N, ctx, da, db):
     b = rng.integers(0, P, db + 1, dtype=np.uint32)
     c = host(N.polymul(ctx, pid, dev(a), dev(b)))
     assert c.size == da + db + 1
-    for x in rng.integers(2, P, 3).tolist():
-        assert oracle.horner(P, c, x) == oracle.horner(P, a, x) * oracle.horner(P, b, x) % P
+    want = oracle.polymul(P, a, b)
+    bad = np.flatnonzero(c != want)
+    assert bad.size == 0, (bad.size, bad[:8].tolist())
+
+
+def test_lengths_above_the_cap_are_refused(N, ctx):
+    """Transforms are capped at 2^23: a product of length 2^23 + 1 and a
+    2^24-point transform return MONT_ENOROOT (the tables end at 2^23), and no
+    context holds longer tables."""
+    from paper_1609_00999_amd import mont
+    x = dev(np.ones((1 << 22) + 1, dtype=np.uint32))
+    with pytest.raises(mont.MontError) as ei:
+        N.polymul(ctx, 0, x, x)                    # da + db + 1 = 2^23 + 1
+    assert ei.value.status == -3
+    z = dev(np.zeros(1 << 24, dtype=np.uint32))
+    with pytest.raises(mont.MontError) as ei:
+        N.forward(ctx, 0, z)
+    assert ei.value.status == -3
+    with pytest.raises(mont.MontError) as ei:
+        N.Context([2013265921], 24)                # v2(P - 1) = 27, but the cap is 23
+    assert ei.value.status == -1
 
 
 def test_polymul_errors(N, ctx):
@@ -202,6 +221,23 @@ def run_plan(N, ctx, batch, grid=0, order_seed=0, spin_limit=0):
     res = host(out)
     plan.close()
     return st, res
+
+
+def assert_batch_exact(batch, got):
+    """Every coefficient of every product of the batch against the oracle,
+    products spread over host threads (longest first)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def check(i):
+        P, a, b = batch.operands(i)
+        c0 = int(batch.c_off[i])
+        ref = oracle.polymul(P, a, b)
+        return -1 if np.array_equal(got[c0:c0 + ref.size], ref) else i
+
+    order = np.argsort(-(batch.da + batch.db), kind="stable")
+    with ThreadPoolExecutor(oracle.default_threads()) as ex:
+        bad = [i for i in ex.map(check, order.tolist()) if i >= 0]
+    assert not bad, bad[:10]
 
 
 def oracle_batch(batch):
@@ -267,10 +303,21 @@ def test_batch_timeout_path_drains(N, ctx):
     assert st == 0 and np.array_equal(got, ref)
 
 
+def run_one_call(N, ctx, batch, scratch=None):
+    """The batch through ntt_polymul_batch (descriptors planned on the device)."""
+    descs = N.make_descs(batch.prime_id, batch.da, batch.db, batch.a_off, batch.b_off, batch.c_off)
+    if scratch is None:
+        scratch = torch.empty((N.batch_scratch_bytes(ctx, descs) + 3) // 4, dtype=torch.int32, device="cuda")
+    out = torch.zeros(max(1, batch.out_len), dtype=torch.int32, device="cuda")
+    N.polymul_batch(ctx, N.descs_to_device(descs), batch.count, dev(batch.coeffs), out, scratch)
+    return N.batch_status(scratch), host(out)
+
+
 def test_batch_config_full_size(N, ctx):
     """2048 products, degrees log-uniform in [2^8, 2^20), eight primes, one
-    persistent launch.  Every product is checked by Schwartz-Zippel at two
-    points; a sample is compared coefficient by coefficient."""
+    persistent launch: every coefficient of every product compared with the
+    oracle (host threads over products); the one-call batch planned on the
+    device gives the same bytes."""
     batch = wl.polymul_batch()
     plan = N.Plan.from_batch(ctx, batch)
     din = dev(batch.coeffs)
@@ -280,33 +327,17 @@ def test_batch_config_full_size(N, ctx):
     assert plan.status(scr) == 0
     got = host(out)
     plan.close()
-    del scr, din
-    from concurrent.futures import ThreadPoolExecutor
-    rng = np.random.default_rng(77)
-    pts = rng.integers(2, 1 << 30, (batch.count, 2))
-
-    def check(i):
-        P, a, b = batch.operands(i)
-        c = got[batch.c_off[i]: batch.c_off[i] + a.size + b.size - 1]
-        for x in pts[i].tolist():
-            if oracle.horner(P, c, x) != oracle.horner(P, a, x) * oracle.horner(P, b, x) % P:
-                return i
-        return -1
-
-    with ThreadPoolExecutor(oracle.default_threads()) as ex:
-        bad = [i for i in ex.map(check, range(batch.count)) if i >= 0]
-    assert not bad, bad[:10]
-    order = np.argsort(batch.da)
-    sample = list(order[:24]) + list(order[-3:]) + list(rng.choice(batch.count, 5, replace=False))
-    jobs = [batch.operands(i) for i in sample]
-    for i, ref in zip(sample, oracle.polymul_many(jobs)):
-        assert np.array_equal(got[batch.c_off[i]: batch.c_off[i] + ref.size], ref), i
+    del scr, din, out
+    assert_batch_exact(batch, got)
+    st, one = run_one_call(N, ctx, batch)
+    assert st == 0
+    assert one[:batch.out_len].tobytes() == got.tobytes()
 
 
 def test_batch_longest_lengths(N, ctx):
     """One persistent launch holding unsplit products of transform lengths
     2^22 and 2^23 (the longest compile-time column tiles) beside short ones:
-    Schwartz-Zippel at three points per product."""
+    every coefficient against the oracle."""
     # none of these meets the split rule: the top product would be longer than N/4
     da = np.array([1500000, (1 << 22) - 1, (1 << 21) - 1, 3000, 120000, 14000], dtype=np.int64)
     db = np.array([1500000, (1 << 22) - 1, 1 << 20, 2000, 120000, 14100], dtype=np.int64)
@@ -319,11 +350,7 @@ def test_batch_longest_lengths(N, ctx):
     assert nsplit == 0
     st, got = run_plan(N, ctx, batch)
     assert st == 0
-    for i in range(batch.count):
-        P, a, b = batch.operands(i)
-        c = got[batch.c_off[i]: batch.c_off[i] + a.size + b.size - 1]
-        for x in rng.integers(2, P, 3).tolist():
-            assert oracle.horner(P, c, x) == oracle.horner(P, a, x) * oracle.horner(P, b, x) % P, i
+    assert_batch_exact(batch, got)
 
 
 def test_batch_graph_replay(N, ctx):
@@ -505,3 +532,123 @@ def test_plan_work_counts(N, ctx):
     assert plan.work() == (want, nsplit)
     assert nsplit > 0
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# One-call batches planned on the device (ntt_polymul_batch)
+# ---------------------------------------------------------------------------
+
+def test_one_call_batch_vs_oracle(N, ctx):
+    """Uneven batches, split shapes and a batch of single-task products
+    through the one-call entry point: every coefficient against the oracle."""
+    rng = np.random.default_rng(91)
+    split = wl.pack_products(PRIMES, rng.integers(0, len(PRIMES), len(SPLIT_SHAPES)),
+                             [x[0] for x in SPLIT_SHAPES], [x[1] for x in SPLIT_SHAPES], rng)
+    for batch in (small_batch(96, 0, 17, 41), split, small_batch(300, 0, 13, 92), small_batch(1, 20, 21, 93)):
+        st, got = run_one_call(N, ctx, batch)
+        assert st == 0
+        assert_batch_exact(batch, got)
+
+
+def test_one_call_equals_plan_bytes(N, ctx):
+    """The device planner and the host planner give the same bytes (the
+    pipelined host order included) on a batch of many multi-pass products."""
+    batch = small_batch(160, 13, 15, 43)
+    st, plan_out = run_plan(N, ctx, batch)
+    assert st == 0
+    st, one = run_one_call(N, ctx, batch)
+    assert st == 0
+    assert one[:batch.out_len].tobytes() == plan_out[:batch.out_len].tobytes()
+
+
+def test_one_call_scratch_bytes_match_the_planner(N, ctx):
+    """ntt_scratch_bytes is exact: with one word less the planning kernel
+    reports MONT_ENOMEM and computes nothing; with exactly that many bytes
+    the batch is exact."""
+    batch = small_batch(40, 4, 18, 94)
+    descs = N.make_descs(batch.prime_id, batch.da, batch.db, batch.a_off, batch.b_off, batch.c_off)
+    need = N.batch_scratch_bytes(ctx, descs)
+    assert need % 4 == 0
+    scr = torch.empty(need // 4, dtype=torch.int32, device="cuda")
+    st, got = run_one_call(N, ctx, batch, scratch=scr)
+    assert st == 0
+    assert_batch_exact(batch, got)
+    st, got = run_one_call(N, ctx, batch, scratch=scr[:need // 4 - 1])
+    assert st == -4
+    assert not np.any(got)
+
+
+def test_one_call_errors(N, ctx):
+    from paper_1609_00999_amd import mont
+    batch = small_batch(5, 4, 12, 95)
+    descs = N.make_descs(batch.prime_id, batch.da, batch.db, batch.a_off, batch.b_off, batch.c_off)
+    scr = torch.empty((N.batch_scratch_bytes(ctx, descs) + 3) // 4, dtype=torch.int32, device="cuda")
+    out = torch.zeros(batch.out_len, dtype=torch.int32, device="cuda")
+    din = dev(batch.coeffs)
+    for field, value, status in (("prime_id", 8, -1), ("reserved", 1, -1), ("da", 1 << 31, -2)):
+        bad = descs.copy()
+        bad[field][3] = value
+        with pytest.raises(ValueError):
+            N.batch_scratch_bytes(ctx, bad)
+        N.polymul_batch(ctx, N.descs_to_device(bad), len(bad), din, out, scr)
+        assert N.batch_status(scr) == status, field
+        assert not torch.any(out)                     # nothing computed
+    small_ctx = N.Context(PRIMES[:1], 12)
+    try:
+        long = descs.copy()
+        long["prime_id"] = 0
+        long["da"][0] = long["db"][0] = 3000              # length 6001 > 2^12
+        N.polymul_batch(small_ctx, N.descs_to_device(long), len(long), din, out, scr)
+        assert N.batch_status(scr) == -3
+    finally:
+        small_ctx.close()
+    with pytest.raises(mont.MontError) as ei:
+        N.polymul_batch(ctx, N.descs_to_device(descs), len(descs), din, out, scr[:16])
+    assert ei.value.status == -4
+    # an empty batch is planned (status OK) and computes nothing
+    N.polymul_batch(ctx, N.descs_to_device(descs[:0]), 0, din, out, scr)
+    assert N.batch_status(scr) == 0
+
+
+def test_one_call_graph_replays_new_descriptors(N, ctx):
+    """The one-call batch captured once in a graph: each replay plans the
+    descriptors the device buffer holds at that moment, so a second batch of
+    the same count runs through the same graph; every replay is exact, with
+    eager work and synchronizations in between."""
+    b1 = small_batch(24, 6, 18, 96)
+    b2 = small_batch(24, 2, 19, 97)
+    d1 = N.make_descs(b1.prime_id, b1.da, b1.db, b1.a_off, b1.b_off, b1.c_off)
+    d2 = N.make_descs(b2.prime_id, b2.da, b2.db, b2.a_off, b2.b_off, b2.c_off)
+    words = max(N.batch_scratch_bytes(ctx, d1), N.batch_scratch_bytes(ctx, d2)) // 4
+    scr = torch.empty(words, dtype=torch.int32, device="cuda")
+    nin = max(b1.coeffs.size, b2.coeffs.size)
+    nout = max(b1.out_len, b2.out_len)
+    din = torch.zeros(nin, dtype=torch.int32, device="cuda")
+    out = torch.zeros(nout, dtype=torch.int32, device="cuda")
+    ddesc = N.descs_to_device(d1)
+    din[:b1.coeffs.size].copy_(dev(b1.coeffs))
+    N.polymul_batch(ctx, ddesc, 24, din, out, scr)
+    assert N.batch_status(scr) == 0
+    eager1 = host(out)[:b1.out_len].copy()
+    assert_batch_exact(b1, eager1)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        N.polymul_batch(ctx, ddesc, 24, din, out, scr)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        N.polymul_batch(ctx, ddesc, 24, din, out, scr)
+    for rep, (b, d) in enumerate([(b2, d2), (b1, d1), (b2, d2)]):
+        ddesc.copy_(N.descs_to_device(d))
+        din.zero_()
+        din[:b.coeffs.size].copy_(dev(b.coeffs))
+        out.zero_()
+        scr.fill_(-1)                          # eager work that dirties the header and counters
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert N.batch_status(scr) == 0, rep
+        assert_batch_exact(b, host(out))
+    del g

@@ -213,3 +213,68 @@ def test_serving_arena_fallback_and_kept_set(mods, ctx):
         else:
             assert j.result is None
     ex.close()
+
+
+def test_serving_full_size_stream(mods, ctx):
+    """The first 300 requests of the serving workload at its full sizes
+    (elementwise n log-uniform in 2^10..2^24, polynomial degree in
+    2^10..2^22, eight primes, Poisson arrivals at 20k requests/s, seed 5),
+    served by the batching loop: every element of every result against the
+    oracle, and the longest polynomial requests alone equal to the mix."""
+    serve = mods[2]
+    reqs = wl.request_stream(300, 20000.0, seed=wl.SEED_SERVE)
+    assert max(r.size for r in reqs if r.kind == "polymul") > 1 << 21
+    assert max(r.size for r in reqs if r.kind == "mul") > 1 << 23
+    inputs = serve.DeviceInputs(reqs, PRIMES)
+    for r in reqs:
+        a0, b0, _ = inputs.offs[r.rid]
+        assert a0 % 4 == 0 and b0 % 4 == 0          # both operands 16-byte aligned
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=4, max_batch=64)
+    stats = serve.Scheduler(ex, slots=4, budget_bytes=16 << 30, max_batch=64).run(serve.jobs_from_requests(reqs))
+    assert all(j.status == serve.OK for j in stats.jobs)
+    mix = {j.rid: host(j.result) for j in stats.jobs}
+    from concurrent.futures import ThreadPoolExecutor
+
+    def check(r):
+        return -1 if np.array_equal(mix[r.rid], oracle_result(inputs, r)) else r.rid
+
+    order = sorted(reqs, key=lambda r: -r.size if r.kind == "polymul" else 0)
+    with ThreadPoolExecutor(oracle.default_threads()) as pool:
+        bad = [rid for rid in pool.map(check, order) if rid >= 0]
+    assert not bad, bad[:10]
+    longest = sorted((r for r in reqs if r.kind == "polymul"), key=lambda r: -r.size)[:3]
+    st = serve.Scheduler(ex, slots=4, budget_bytes=16 << 30).run(serve.jobs_from_requests(longest))
+    for j in st.jobs:
+        assert j.status == serve.OK
+        assert host(j.result).tobytes() == mix[j.rid].tobytes()
+    ex.close()
+
+
+def test_serving_executor_reports_device_timeouts(mods, ctx):
+    """The batching executor with a one-sleep bound on the transform tasks'
+    dependency waits: batches holding long products time out on the device
+    (every kernel still exits), and exactly their polynomial requests come
+    back FAILED with MONT_ETIMEOUT, while elementwise requests stay exact.
+    The same executor then serves the stream exactly with the normal bound."""
+    serve = mods[2]
+    reqs = wl.request_stream(12, 1e6, seed=21, mul_log2=(10, 14), poly_log2=(17, 19))
+    for r in reqs:
+        r.t_arrival = 0.0
+    inputs = serve.DeviceInputs(reqs, PRIMES)
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=2, max_batch=4, spin_limit=1)
+    st = serve.Scheduler(ex, slots=2, budget_bytes=1 << 32, max_batch=4).run(serve.jobs_from_requests(reqs))
+    failed = [j for j in st.jobs if j.status == serve.FAILED]
+    assert failed, "long products with a one-sleep wait bound should time out"
+    for j in st.jobs:
+        if j.status == serve.FAILED:
+            assert j.kind == "polymul" and "MONT_ETIMEOUT" in j.error and j.result is None
+        else:
+            assert j.status == serve.OK
+            assert np.array_equal(host(j.result), oracle_result(inputs, reqs[j.rid])), j.rid
+    assert all(j.status == serve.OK for j in st.jobs if j.kind == "mul")
+    ex.spin_limit = 0
+    st = serve.Scheduler(ex, slots=2, budget_bytes=1 << 32, max_batch=4).run(serve.jobs_from_requests(reqs))
+    assert all(j.status == serve.OK for j in st.jobs)
+    for j in st.jobs:
+        assert np.array_equal(host(j.result), oracle_result(inputs, reqs[j.rid])), j.rid
+    ex.close()
