@@ -88,6 +88,26 @@ MONT_API mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint32_
                                  const uint32_t* d_b, uint32_t db, uint32_t* d_out, void* d_scratch,
                                  size_t scratch_bytes, void* stream);
 
+/*
+ * ntt_polymul_noalloc -- ntt_polymul for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same launches and the same result, with the transform
+ * scratch taken from a static 16 MiB device array that the library holds on
+ * each device until the process ends, so the call allocates nothing and
+ * takes no scratch argument.  Limit: transform length N <= 2^21 (da+db+1 <=
+ * 2^21); longer products return MONT_ENOMEM.  The array's device address is
+ * looked up when ntt_ctx_create runs on the device; the call must be made
+ * with the context's device current (MONT_EINVAL otherwise).  Every call on
+ * one device shares that one array, so calls that overlap on a device (on
+ * different streams, or from several threads without ordering) race and
+ * give wrong results; calls ordered on one stream are safe.  The scratch
+ * needs no clearing: each call writes it before reading it.  Errors: those
+ * of ntt_polymul, MONT_ENOMEM above the limit, MONT_EHIP if the array's
+ * address could not be looked up.
+ */
+MONT_API mont_status ntt_polymul_noalloc(const ntt_ctx* ctx, int prime_id, const uint32_t* d_a, uint32_t da,
+                                         const uint32_t* d_b, uint32_t db, uint32_t* d_out, void* stream);
+
 /* One product of a batch: operands at d_in + a_off (da+1 words) and
  * d_in + b_off (db+1 words), result at d_out + c_off (da+db+1 words). */
 typedef struct polymul_desc {

@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <random>
@@ -1460,6 +1461,37 @@ bool is_prime_host(uint32_t P) {
 
 using namespace mont;
 
+// Scratch of the allocation-free product (ntt_polymul_noalloc): the two
+// length-N transforms of one product of N <= 2^21, 16 MiB, one copy on every
+// device the library runs on, held until the process ends.  In host code the
+// array's name is only a host-side stand-in; its device address is looked
+// up once per device with hipGetSymbolAddress (noalloc_scratch_on) and only
+// that address is used.
+constexpr int kNoAllocLog = 21;
+static __device__ __align__(256) uint32_t noalloc_scratch[(size_t)2 << kNoAllocLog];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+uint32_t* g_noalloc_ptr[kNoAllocDevices] = {};
+
+// Device address of noalloc_scratch on `device`, which must be current.
+mont_status noalloc_scratch_on(int device, uint32_t** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kNoAllocDevices) return MONT_EHIP;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) return MONT_EHIP;
+    g_noalloc_ptr[device] = static_cast<uint32_t*>(p);
+  }
+  *out = g_noalloc_ptr[device];
+  return MONT_OK;
+}
+
+}  // namespace
+
 struct ntt_ctx {
   int device = 0;
   int log2_nmax = 0;
@@ -1469,6 +1501,7 @@ struct ntt_ctx {
   std::vector<uint32_t*> twf, twi;  // device pointers into tw_mem
   PrimeDev* d_primes = nullptr;
   uint32_t* tw_mem = nullptr;
+  uint32_t* noalloc_scr = nullptr;  // this device's noalloc_scratch (nullptr if the lookup failed)
 };
 
 struct ntt_plan {
@@ -1681,6 +1714,9 @@ extern "C" mont_status ntt_ctx_create(const uint32_t* primes, int nprimes, int l
     delete ctx;
     return st;
   }
+  // the allocation-free product's scratch on this device; a failed lookup
+  // only disables that entry point (it then returns MONT_EHIP)
+  if (noalloc_scratch_on(ctx->device, &ctx->noalloc_scr) != MONT_OK) ctx->noalloc_scr = nullptr;
   *out = ctx;
   return MONT_OK;
 }
@@ -1761,17 +1797,12 @@ extern "C" size_t ntt_polymul_scratch_bytes(uint32_t da, uint32_t db) {
   return n <= kRowLog ? 0 : (size_t)8 << n;
 }
 
-extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint32_t* d_a, uint32_t da,
-                                   const uint32_t* d_b, uint32_t db, uint32_t* d_out, void* d_scratch,
-                                   size_t scratch_bytes, void* stream) {
-  if (!prime_ok(ctx, prime_id) || !d_a || !d_b || !d_out) return MONT_EINVAL;
-  if ((uint64_t)da + db + 1 > ((uint64_t)1 << 31)) return MONT_ERANGE;
-  int n = ceil_log2((uint64_t)da + db + 1);
-  if ((uint32_t)n > ctx->logmax[prime_id]) return MONT_ENOROOT;
-  size_t need = ntt_polymul_scratch_bytes(da, db);
-  if (need && (!d_scratch || scratch_bytes < need)) return MONT_ENOMEM;
-  if (need && !aligned16(d_scratch)) return MONT_EINVAL;
-  hipStream_t s = as_stream(stream);
+namespace {
+
+// The plain-launch product on scratch scr (2N words when N > 2^13), after
+// the caller's validation.
+mont_status polymul_launch(const ntt_ctx* ctx, int prime_id, int n, const uint32_t* d_a, uint32_t da,
+                           const uint32_t* d_b, uint32_t db, uint32_t* d_out, uint32_t* scr, hipStream_t s) {
   (void)hipGetLastError();
   DirectArgs g = direct_base(ctx, prime_id, n);
   g.a = d_a;
@@ -1779,7 +1810,7 @@ extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint3
   g.da = da;
   g.db = db;
   g.out = d_out;
-  g.scr = static_cast<uint32_t*>(d_scratch);
+  g.scr = scr;
   if (n <= kRowLog) {
     g.kind = D_SMALL_POLY;
     launch_direct(g, 1, s);
@@ -1792,6 +1823,36 @@ extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint3
     launch_direct(g, g.ntiles, s);
   }
   return last_launch_status();
+}
+
+}  // namespace
+
+extern "C" mont_status ntt_polymul(const ntt_ctx* ctx, int prime_id, const uint32_t* d_a, uint32_t da,
+                                   const uint32_t* d_b, uint32_t db, uint32_t* d_out, void* d_scratch,
+                                   size_t scratch_bytes, void* stream) {
+  if (!prime_ok(ctx, prime_id) || !d_a || !d_b || !d_out) return MONT_EINVAL;
+  if ((uint64_t)da + db + 1 > ((uint64_t)1 << 31)) return MONT_ERANGE;
+  int n = ceil_log2((uint64_t)da + db + 1);
+  if ((uint32_t)n > ctx->logmax[prime_id]) return MONT_ENOROOT;
+  size_t need = ntt_polymul_scratch_bytes(da, db);
+  if (need && (!d_scratch || scratch_bytes < need)) return MONT_ENOMEM;
+  if (need && !aligned16(d_scratch)) return MONT_EINVAL;
+  return polymul_launch(ctx, prime_id, n, d_a, da, d_b, db, d_out, static_cast<uint32_t*>(d_scratch),
+                        as_stream(stream));
+}
+
+extern "C" mont_status ntt_polymul_noalloc(const ntt_ctx* ctx, int prime_id, const uint32_t* d_a, uint32_t da,
+                                           const uint32_t* d_b, uint32_t db, uint32_t* d_out, void* stream) {
+  if (!prime_ok(ctx, prime_id) || !d_a || !d_b || !d_out) return MONT_EINVAL;
+  if ((uint64_t)da + db + 1 > ((uint64_t)1 << 31)) return MONT_ERANGE;
+  const int n = ceil_log2((uint64_t)da + db + 1);
+  if ((uint32_t)n > ctx->logmax[prime_id]) return MONT_ENOROOT;
+  if (n > kNoAllocLog) return MONT_ENOMEM;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MONT_EHIP;
+  if (dev != ctx->device) return MONT_EINVAL;
+  if (!ctx->noalloc_scr) return MONT_EHIP;
+  return polymul_launch(ctx, prime_id, n, d_a, da, d_b, db, d_out, ctx->noalloc_scr, as_stream(stream));
 }
 
 // ---------------------------------------------------------------------------

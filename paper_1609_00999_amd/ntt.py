@@ -56,6 +56,7 @@ def register(L) -> None:
     L.ntt_plan_execute.argtypes = [c_vp, c_vp, c_vp, c_vp, c_size, c_int, c_u32, c_vp]
     L.ntt_plan_status.argtypes = [c_vp, c_vp, c_vp]
     L.ntt_plan_status_async.argtypes = [c_vp, c_vp, c_vp, c_vp]
+    L.ntt_polymul_noalloc.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp, c_u32, c_vp, c_vp]
     L.ntt_scratch_bytes.argtypes = [c_vp, c_vp, c_int]
     L.ntt_scratch_bytes.restype = c_size
     L.ntt_polymul_batch.argtypes = [c_vp, c_vp, c_int, c_vp, c_vp, c_vp, c_size, c_vp]
@@ -171,6 +172,20 @@ def polymul(ctx: Context, prime_id: int, a, b, out=None, scratch=None):
     sb = scratch.numel() * scratch.element_size() if need else 0
     mont.check(mont.lib().ntt_polymul(ctx.handle, prime_id, mont.dev_ptr(a, "a"), da, mont.dev_ptr(b, "b"), db,
                                       mont.dev_ptr(out, "out"), sp, sb, mont.stream_handle()), "ntt_polymul")
+    return out
+
+
+def polymul_noalloc(ctx: Context, prime_id: int, a, b, out, stream=None):
+    """ntt_polymul_noalloc: the product into the caller's `out` (da+db+1
+    words) with the library's static scratch (transform length <= 2^21)."""
+    if a.numel() == 0 or b.numel() == 0:
+        raise ValueError("empty polynomial")
+    da, db = a.numel() - 1, b.numel() - 1
+    if out.numel() != da + db + 1:
+        raise ValueError("out must hold da+db+1 coefficients")
+    mont.check(mont.lib().ntt_polymul_noalloc(ctx.handle, prime_id, mont.dev_ptr(a, "a"), da, mont.dev_ptr(b, "b"),
+                                              db, mont.dev_ptr(out, "out"), mont.stream_handle(stream)),
+               "ntt_polymul_noalloc")
     return out
 
 
