@@ -24,22 +24,32 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRCS = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "oracle64.c")]
-_LIB = os.path.join(_HERE, "liboracle.so")
+_DEFAULT_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of the same sources to load instead (the
+# sanitizer test loads an address- and undefined-behaviour-sanitized one).
+_LIB = os.environ.get("ORACLE_LIB") or _DEFAULT_LIB
 
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c and oracle64.c with gcc into liboracle.so next to them."""
-    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+def build(force: bool = False, out: str | None = None, extra_flags=()) -> str:
+    """Compile oracle.c and oracle64.c with gcc into liboracle.so next to them
+    (or into `out`, with extra compiler flags such as sanitizers)."""
+    out = out or _DEFAULT_LIB
+    stale = not os.path.exists(out) or any(os.path.getmtime(out) < os.path.getmtime(f) for f in _SRCS)
     if force or stale:
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", "-shared", "-fPIC",
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-Wextra", *extra_flags, "-shared", "-fPIC",
                                "-o", tmp, *_SRCS])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def loaded_path() -> str:
+    """Path of the oracle library this process loaded."""
+    return _load()._name
 
 
 def _load():
@@ -47,6 +57,8 @@ def _load():
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB):
+        if _LIB != _DEFAULT_LIB:
+            raise FileNotFoundError("ORACLE_LIB=%s does not exist" % _LIB)
         build()
     lib = ctypes.CDLL(_LIB)
     sz = ctypes.c_size_t

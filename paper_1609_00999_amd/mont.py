@@ -85,8 +85,10 @@ def _apply_tuning(L) -> None:
             return
         from . import tune
         tune.applied = tune.apply(tune.load(), tune.device_arch(), L)
-    except Exception:   # tuning is an optimisation; defaults stay in force
-        pass
+    except Exception as e:   # tuning is an optimisation: say so, keep the defaults
+        import warnings
+        warnings.warn("libmont tuning not applied (%s: %s); built-in launch shapes stay in force"
+                      % (type(e).__name__, e), RuntimeWarning)
 
 
 def _register_ntt(L):

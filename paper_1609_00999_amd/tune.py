@@ -22,6 +22,7 @@ import argparse
 import json
 import os
 import time
+import warnings
 
 import numpy as np
 
@@ -39,13 +40,22 @@ def cache_path() -> str:
 
 
 def load(path: str | None = None) -> dict:
+    """The tuning cache ({} if there is none yet).  A cache that exists but
+    cannot be read or parsed is reported with a RuntimeWarning and ignored."""
     path = path or cache_path()
+    if not os.path.exists(path):
+        return {}
     try:
         with open(path) as f:
             data = json.load(f)
-        return data if isinstance(data, dict) else {}
-    except (OSError, ValueError):
+    except (OSError, ValueError) as e:
+        warnings.warn("libmont tuning cache %s not loaded (%s); built-in launch shapes stay in force"
+                      % (path, e), RuntimeWarning)
         return {}
+    if not isinstance(data, dict):
+        warnings.warn("libmont tuning cache %s is not a JSON object; ignored" % path, RuntimeWarning)
+        return {}
+    return data
 
 
 def save(cache: dict, path: str | None = None) -> str:
@@ -87,13 +97,36 @@ def apply(cache: dict, arch: str, lib) -> dict:
     """Set the tuned launch shapes of `arch` through the C ABI; returns what
     was applied."""
     applied = {}
+
+    def rejected(family, cfg, why):
+        warnings.warn("libmont tuning cache entry %s %r for %s not applied (%s)" % (family, cfg, arch, why),
+                      RuntimeWarning)
+
     for op, idx in (("to", 0), ("from", 1), ("mul", 2), ("muladd", 3), ("pow", 4), ("modmul", 5)):
-        cfg = choose(cache, arch, "elem_" + op)
-        if cfg and lib.mont_elem_tune_set(idx, int(cfg[0]), int(cfg[1]), int(cfg[2])) == 0:
-            applied["elem_" + op] = cfg
+        fam = "elem_" + op
+        cfg = choose(cache, arch, fam)
+        if not cfg:
+            continue
+        try:
+            st = lib.mont_elem_tune_set(idx, int(cfg[0]), int(cfg[1]), int(cfg[2]))
+        except (TypeError, ValueError, IndexError) as e:
+            rejected(fam, cfg, e)
+            continue
+        if st == 0:
+            applied[fam] = cfg
+        else:
+            rejected(fam, cfg, "status %d" % st)
     cfg = choose(cache, arch, "ntt")
-    if cfg and lib.ntt_tune_set(int(cfg[0]), int(cfg[1]), int(cfg[2])) == 0:
-        applied["ntt"] = cfg
+    if cfg:
+        try:
+            st = lib.ntt_tune_set(int(cfg[0]), int(cfg[1]), int(cfg[2]))
+        except (TypeError, ValueError, IndexError) as e:
+            st = None
+            rejected("ntt", cfg, e)
+        if st == 0:
+            applied["ntt"] = cfg
+        elif st is not None:
+            rejected("ntt", cfg, "status %d" % st)
     return applied
 
 

@@ -1,6 +1,9 @@
-"""The paper's Algorithms 1 and 3 written out step by step in Python integers,
-checked against plain modular arithmetic (CPU).  They pin the readings of
-section 3.1 that the device kernels rely on, and the new oracle routines."""
+"""Facts of section 3.1 behind Algorithms 1 and 3, stated from the
+mathematics in Python integers and checked against plain modular arithmetic
+(CPU): the quantities the algorithms form, the ranges they stay in and the
+congruences they satisfy.  They pin the readings the device kernels rely on
+(the borrow form of Algorithm 3, the two-subtraction form of Algorithm 1) and
+the oracle's plain routines."""
 import numpy as np
 import pytest
 
@@ -11,12 +14,6 @@ R = 1 << 32
 FOURIER = sorted(set(wl.PRIMES_BW) | set(wl.PRIMES_NTT))
 
 
-def i32(x):
-    """Two's-complement 32-bit reading of an integer."""
-    x &= 0xFFFFFFFF
-    return x - (1 << 32) if x & 0x80000000 else x
-
-
 def fourier_parts(a, b, P):
     """q1, q2, q3 of Algorithm 3 with K = c 2^k = P - 1, and the dropped r3."""
     K = P - 1
@@ -25,16 +22,6 @@ def fourier_parts(a, b, P):
     q2, r2 = (K * r1) // R, (K * r1) % R
     q3, r3 = (K * r2) // R, (K * r2) % R
     return q1, q2, q3, r3
-
-
-def alg3_as_printed(a, b, P):
-    """Algorithm 3 with its 32-bit signed sign-mask corrections."""
-    q1, q2, q3, _ = fourier_parts(a, b, P)
-    t = i32(q1 - q2 + q3)
-    t = i32(t + ((t >> 31) & P))          # Python >> on a negative int is arithmetic
-    t = i32(t - P)
-    t = i32(t + ((t >> 31) & P))
-    return t
 
 
 def alg3_borrow(a, b, P):
@@ -75,40 +62,52 @@ def test_alg3_borrow_form_matches_redc(P):
     assert [alg3_borrow(x, y, P) for x, y in zip(a, b)] == ref
 
 
-def test_alg3_as_printed_overflows_for_31_bit_primes():
-    """The printed corrections are exact while 2(P-1) < 2^31 and fail beyond."""
-    for P in (469762049, 998244353):                   # 29- and 30-bit
+def test_alg3_sum_fits_a_signed_word_only_below_31_bits():
+    """Algorithm 3 decides its corrections from the sign of q1 - q2 + q3 (and
+    of that sum minus P) held in one signed 32-bit word.  The sum's range
+    (-(P-1), 2(P-1)) fits a signed word only when 2(P-1) <= 2^31 - 1: for the
+    29- and 30-bit primes every sum and every sum minus P is representable,
+    while for the 31-bit primes sums of 2^31 and more occur, which a signed
+    32-bit word would read as negative.  Hence the kernel's unsigned borrow
+    form."""
+    lim = 1 << 31
+    for P in (469762049, 998244353):
         a, b = samples(P, seed=2)
-        ref = oracle.mont_mul(P, np.array(a, dtype=np.uint32), np.array(b, dtype=np.uint32)).tolist()
-        assert [alg3_as_printed(x, y, P) for x, y in zip(a, b)] == ref
-    for P in (2013265921, 2113929217):                 # 31-bit: q1 - q2 + q3 can exceed 2^31
+        for x, y in zip(a, b):
+            q1, q2, q3, _ = fourier_parts(x, y, P)
+            t = q1 - q2 + q3
+            assert -lim <= t < lim and -lim <= t - P < lim
+    for P in (2013265921, 2113929217):
         a, b = samples(P, seed=3)
-        ref = oracle.mont_mul(P, np.array(a, dtype=np.uint32), np.array(b, dtype=np.uint32)).tolist()
-        bad = sum(alg3_as_printed(x, y, P) != r for x, y, r in zip(a, b, ref))
-        assert bad > 0
+        tops = [sum(fourier_parts(x, y, P)[i] * (1, -1, 1)[i] for i in range(3)) for x, y in zip(a, b)]
+        assert max(tops) >= lim
+        assert 2 * (P - 1) > lim - 1
 
 
-def barrett_as_printed(a, b, P):
-    """Algorithm 1; returns the result and the number of correction loops."""
+def barrett_quantities(a, b, P):
+    """Algorithm 1's quantities from their definitions: k the bit length of P,
+    the precomputed floor(2^2k / P), the quotient estimate q = floor(floor(ab /
+    2^k) floor(2^2k / P) / 2^k) and the remainder t = ab - qP."""
     k = P.bit_length()                                 # ceil(log2 P) for P not a power of two
-    Pb = (1 << (2 * k)) // P
-    m = (a * b) >> k
-    q = (m * Pb) >> k
-    t = a * b - q * P
-    assert 0 <= t < 4 * P
-    loops = 0
-    while t >= P:
-        t -= P
-        loops += 1
-    return t, loops
+    inv = (1 << (2 * k)) // P
+    q = (((a * b) >> k) * inv) >> k
+    return q, a * b - q * P
 
 
 @pytest.mark.parametrize("P", FOURIER + [3, 17, 65537, (1 << 31) - 1, 1000003])
-def test_barrett_matches_plain_product(P):
+def test_barrett_quotient_bound(P):
+    """The quotient estimate undershoots floor(ab / P) by at most 3, so the
+    remainder t = ab - qP lies in [0, 4P) and is congruent to ab: at most three
+    subtractions of P finish the reduction (one of 2P and one of P in the
+    kernel's form), and t < 4P < 2^33 bounds the intermediate."""
     a, b = samples(P, seed=4)
-    got = [barrett_as_printed(x, y, P) for x, y in zip(a, b)]
-    assert [g[0] for g in got] == [x * y % P for x, y in zip(a, b)]
-    assert max(g[1] for g in got) <= 3
+    for x, y in zip(a, b):
+        q, t = barrett_quantities(x, y, P)
+        assert 0 <= (x * y) // P - q <= 3
+        assert 0 <= t < 4 * P and t % P == x * y % P
+        r = t - 2 * P if t >= 2 * P else t                 # the kernel's two conditional subtractions
+        r = r - P if r >= P else r
+        assert r == x * y % P
 
 
 def test_oracle_plain_routines():

@@ -67,3 +67,35 @@ def test_shape_sets_match_the_abi():
     assert L.ntt_tune_get(ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)) == 0
     L.ntt_tune_set(512, 4, 1)
     L.mont_elem_tune_set(2, 256, 1, 1)
+
+
+def test_cache_problems_are_reported(tmp_path):
+    """A corrupt cache, a cache that is not an object and an entry the library
+    rejects each raise a RuntimeWarning (the built-in shapes stay in force)."""
+    import warnings
+    import pytest
+    bad = os.path.join(str(tmp_path), "bad.json")
+    with open(bad, "w") as f:
+        f.write("{not json")
+    with pytest.warns(RuntimeWarning, match="not loaded"):
+        assert tune.load(bad) == {}
+    lst = os.path.join(str(tmp_path), "list.json")
+    with open(lst, "w") as f:
+        f.write("[1, 2]")
+    with pytest.warns(RuntimeWarning, match="not a JSON object"):
+        assert tune.load(lst) == {}
+
+    class Rejecting(FakeLib):
+        def ntt_tune_set(self, threads, radix, gm):
+            return -1
+
+    cache = {"gfx950": {"elem_mul": {"28": {"config": [512, 2, 1]}}, "ntt": {"b": {"config": [300, 3, 1]}}}}
+    with pytest.warns(RuntimeWarning, match="ntt"):
+        applied = tune.apply(cache, "gfx950", Rejecting())
+    assert applied == {"elem_mul": [512, 2, 1]}
+    broken = {"gfx950": {"elem_to": {"28": {"config": ["x"]}}}}
+    with pytest.warns(RuntimeWarning, match="elem_to"):
+        assert tune.apply(broken, "gfx950", FakeLib()) == {}
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        assert tune.load(os.path.join(str(tmp_path), "missing.json")) == {}   # no cache yet: silent
