@@ -168,6 +168,13 @@ MONT_API uint32_t ntt_plan_task_count(uint32_t da, uint32_t db);
 MONT_API mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs, int count, uint32_t order_seed,
                                      void* stream);
 
+/* Host time of the last ntt_plan_update on a reserved plan, in
+ * microseconds: us[0] planning, us[1] waiting for the previous upload to
+ * leave the staging block, us[2] the upload call (0 when the lists travel in
+ * the launch arguments), us[3] the whole call.  A diagnostic for callers that
+ * budget host latency (a serving loop).  Errors: MONT_EINVAL. */
+MONT_API mont_status ntt_plan_update_times(const ntt_plan* plan, uint32_t* us);
+
 /* Sizes a caller needs: scratch bytes, task count, the minimum lengths (in
  * words) of d_in and d_out, and the default persistent grid (resident
  * workgroups on the device).  Any output pointer may be NULL. */

@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstddef>
 #include <cstring>
 #include <mutex>
@@ -1534,6 +1536,9 @@ struct ntt_plan {
   bool inl = false;
   ProdDev inl_prods[kInlineProds];
   uint2 inl_tasks[kInlineTasks];
+  // host time of the last ntt_plan_update, microseconds: planning, waiting
+  // for the previous upload to leave staging, the upload call, in all
+  uint32_t upd_us[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -1593,15 +1598,37 @@ void launch_persistent(const PlanArgs& g, uint32_t grid, hipStream_t s) {
 }
 
 // Resident persistent workgroups for the current launch shape.
+// Resident workgroups of each launch shape on each device, computed once:
+// the occupancy query costs more host time than a launch, and a serving loop
+// asks for the grid on every update and execution.
+constexpr int kGridDevices = 64;
+std::atomic<int> g_grid_cache[kGridDevices][6];
+
 int persistent_grid() {
-  int dev = 0, cus = 256, per_cu = 1;
+  int dev = 0;
   (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int v = 0, per_cu = 1;
+#define MONT_V(T, R)                                                    \
+  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) break;     \
+  v++;
+  do {
+    MONT_NTT_VARIANTS(MONT_V)
+  } while (0);
+#undef MONT_V
+  if (v > 5) v = 3;                                   // unknown shape: the 512 x 4 default
+  std::atomic<int>* slot = dev >= 0 && dev < kGridDevices ? &g_grid_cache[dev][v] : nullptr;
+  int resident = slot ? slot->load(std::memory_order_relaxed) : 0;
+  if (resident <= 0) {
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 #define MONT_V(T, R) \
   if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) per_cu = occupancy_v<T, R>();
-  MONT_NTT_VARIANTS(MONT_V)
+    MONT_NTT_VARIANTS(MONT_V)
 #undef MONT_V
-  return cus * per_cu * g_ntt_tune.grid_mult;
+    resident = cus * per_cu;
+    if (slot) slot->store(resident, std::memory_order_relaxed);
+  }
+  return resident * g_ntt_tune.grid_mult;
 }
 
 bool prime_ok(const ntt_ctx* ctx, int prime_id) {
@@ -2156,6 +2183,11 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
                                        void* stream) {
   if (!plan || !plan->reusable || count < 0 || (count > 0 && !descs)) return MONT_EINVAL;
   if (count > plan->cap_prods) return MONT_ERANGE;
+  using clock = std::chrono::steady_clock;
+  const auto us_since = [](clock::time_point t) {
+    return (uint32_t)std::chrono::duration_cast<std::chrono::microseconds>(clock::now() - t).count();
+  };
+  const clock::time_point t0 = clock::now();
   std::vector<ProdDev> prods;
   std::vector<uint2> tasks;
   std::vector<FixDev> fixes;
@@ -2166,9 +2198,13 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
                               out_words, redc);
   if (st != MONT_OK) return st;
   if (tasks.size() > plan->cap_tasks) return MONT_ERANGE;
+  plan->upd_us[0] = us_since(t0);
   // The previous upload must have finished reading the staging buffers.
+  const clock::time_point t1 = clock::now();
   if (plan->staged_pending && hipEventSynchronize(plan->staged) != hipSuccess) return MONT_EHIP;
   plan->staged_pending = false;
+  plan->upd_us[1] = us_since(t1);
+  plan->upd_us[2] = 0;
   hipStream_t s = as_stream(stream);
   plan->inl = !prods.empty() && prods.size() <= kInlineProds && tasks.size() <= kInlineTasks && fixes.empty();
   if (plan->inl) {
@@ -2185,9 +2221,11 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
     std::memcpy(h, prods.data(), bp);
     if (bf) std::memcpy(h + bp, fixes.data(), bf);
     if (bt) std::memcpy(h + bp + bf, tasks.data(), bt);
+    const clock::time_point t2 = clock::now();
     if (hipMemcpyAsync(d, h, bp + bf + bt, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipEventRecord(plan->staged, s) != hipSuccess)
       return MONT_EHIP;
+    plan->upd_us[2] = us_since(t2);
     plan->staged_pending = true;
     plan->d_prods = reinterpret_cast<ProdDev*>(d);
     plan->d_fix = reinterpret_cast<FixDev*>(d + bp);
@@ -2201,6 +2239,13 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
+  plan->upd_us[3] = us_since(t0);
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_plan_update_times(const ntt_plan* plan, uint32_t* us) {
+  if (!plan || !us) return MONT_EINVAL;
+  for (int i = 0; i < 4; i++) us[i] = plan->upd_us[i];
   return MONT_OK;
 }
 

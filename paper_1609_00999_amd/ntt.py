@@ -57,6 +57,7 @@ def register(L) -> None:
     L.ntt_plan_status.argtypes = [c_vp, c_vp, c_vp]
     L.ntt_plan_status_async.argtypes = [c_vp, c_vp, c_vp, c_vp]
     L.ntt_polymul_noalloc.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp, c_u32, c_vp, c_vp]
+    L.ntt_plan_update_times.argtypes = [c_vp, ctypes.POINTER(c_u32)]
     L.ntt_scratch_bytes.argtypes = [c_vp, c_vp, c_int]
     L.ntt_scratch_bytes.restype = c_size
     L.ntt_polymul_batch.argtypes = [c_vp, c_vp, c_int, c_vp, c_vp, c_vp, c_size, c_vp]
@@ -240,6 +241,13 @@ class Plan:
         mont.check(mont.lib().ntt_plan_update(self.handle, descs.ctypes.data if len(descs) else None, len(descs),
                                               order_seed, mont.stream_handle(stream)), "ntt_plan_update")
         self._info()
+
+    def update_times_us(self):
+        """Host microseconds of the last update: (planning, wait for the
+        previous upload, upload call, whole call)."""
+        us = (c_u32 * 4)()
+        mont.check(mont.lib().ntt_plan_update_times(self.handle, us), "ntt_plan_update_times")
+        return tuple(us)
 
     def work(self):
         """(REDC per execution as planned, number of split products)."""

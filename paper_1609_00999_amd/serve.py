@@ -268,7 +268,8 @@ class GpuBatchExecutor:
     slot's stream."""
 
     def __init__(self, ctx, inputs: DeviceInputs, slots: int, max_batch: int, keep_results: bool = True,
-                 max_tasks: int = 1 << 20, arena_bytes: int = 1 << 30, spin_limit: int = 0):
+                 max_tasks: int = 1 << 20, arena_bytes: int = 1 << 30, spin_limit: int = 0, warm: bool = True,
+                 single_plain: bool = True):
         import torch
         from . import mont, ntt
         self.torch, self.mont, self.ntt = torch, mont, ntt
@@ -277,6 +278,11 @@ class GpuBatchExecutor:
         self.keep = keep_results
         # bound on a transform task's dependency waits (0: the library default)
         self.spin_limit = int(spin_limit)
+        # A batch holding one polynomial product runs it with ntt_polymul's
+        # plain launches (one per pass, each sized to the product) instead of
+        # a persistent launch: with nothing to overlap, the persistent grid
+        # only adds its task queue and dependency waits to the latency.
+        self.single_plain = bool(single_plain)
         # One pinned status word per slot: each batch's persistent launch
         # copies its status there on the slot's stream before the batch's
         # completion event, so finish() reads it without a synchronization.
@@ -287,6 +293,7 @@ class GpuBatchExecutor:
         self.vecb = [mont.Batch(max_batch) for _ in range(slots)]
         self.plans = [ntt.Plan.reserve(ctx, max_batch, max_tasks) for _ in range(slots)]
         self.max_tasks = max_tasks
+        self.max_batch = max_batch
         dev = inputs.arena.device
         # Per-slot device arenas: a batch carves its outputs and transform
         # scratch from its slot's arena (a slot runs one batch at a time), so
@@ -305,6 +312,55 @@ class GpuBatchExecutor:
             for rid, w in sorted(words.items()):
                 self.kept[rid] = pool[pos:pos + w]
                 pos += _a4(w)
+        # Host-side breakdown of launches slower than 1 ms: (first request id,
+        # seconds in plan update, vector batch, transform launch, the rest).
+        self.slow_launches = []
+        if warm:
+            self.warm()
+
+    def warm(self):
+        """Run every kernel and library path a batch can take once on each
+        slot (vector batches with descriptors in the launch and uploaded, a
+        plan in the launch and an uploaded one with a split product and its
+        fix-up), so that code objects load and first-use costs are paid
+        before the first request instead of inside the request loop."""
+        torch, mont, ntt = self.torch, self.mont, self.ntt
+        dev = self.inputs.arena.device
+        prm = self.params[0]
+        x = torch.ones(1 << 20, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        # one product (lists in the launch), one that the plan splits (lists
+        # uploaded, fix-up kernel), then the largest batch the slot takes of
+        # two-pass products (a large upload: the runtime's copy path for
+        # larger transfers is set up here too, not inside the request loop)
+        nbig = max(2, min(self.max_batch, 64))
+        shapes = ([(64, 64)], [(8200, 8200)],
+                  [((1 << 20) - 1, (1 << 20) - 1)] * 2 + [(9000 + 7 * i, 9000) for i in range(nbig - 2)])
+        for slot in range(len(self.streams)):
+            s = self.streams[slot]
+            for nv in sorted({1, 17, self.vecb[slot].cap} & set(range(1, self.vecb[slot].cap + 1))):
+                descs = (mont.VecDesc * nv)()
+                for i in range(nv):
+                    descs[i] = mont.VecDesc(x.data_ptr() + 64 * i, x.data_ptr() + 64 * i, y.data_ptr() + 64 * i, 16,
+                                            prm.P, prm.Pprime)
+                self.vecb[slot].update_raw(descs, stream=s)
+                self.vecb[slot].mul(stream=s)
+            for shp in shapes:
+                desc = np.zeros(len(shp), dtype=ntt.DESC_DTYPE)
+                cpos = 0
+                for i, (da, db) in enumerate(shp):
+                    desc[i] = (0, da, db, 0, 0, 0, cpos)
+                    cpos += da + db + 1
+                plan = self.plans[slot]
+                plan.update(desc, stream=s)
+                out = torch.empty(max(cpos, 1), dtype=torch.int32, device=dev)
+                scr = torch.empty((plan.scratch_bytes + 3) // 4, dtype=torch.int32, device=dev)
+                plan.execute(x, out, scr, stream=s)
+                plan.status_async(scr, self._status_ptr + 4 * slot, stream=s)
+                s.synchronize()
+                if int(self.status_host[slot]) != 0:
+                    raise RuntimeError("warm-up batch of the serving executor timed out on the device")
+        torch.cuda.synchronize()
 
     def _result_words(self, rid) -> int:
         _, _, n = self.inputs.offs[rid]       # n residues, or d + 1 coefficients
@@ -318,6 +374,9 @@ class GpuBatchExecutor:
 
     def launch(self, slot: int, batch):
         torch, mont, ntt = self.torch, self.mont, self.ntt
+        clk = time.perf_counter
+        t0 = clk()
+        t_plan = t_vec = t_exec = 0.0
         s = self.streams[slot]
         muls = [j for j in batch if j.kind == "mul"]
         polys = [j for j in batch if j.kind == "polymul"]
@@ -325,15 +384,23 @@ class GpuBatchExecutor:
         # Every library call below names the slot's stream explicitly: looking
         # up torch's current stream costs more host time than the call itself.
         plan, desc, cpos = None, None, 0
-        if polys:
+        one = len(polys) == 1 and self.single_plain
+        if one:
+            cpos = 2 * polys[0].size + 1
+        elif polys:
             desc = np.zeros(len(polys), dtype=ntt.DESC_DTYPE)
             for i, j in enumerate(polys):
                 a0, b0, n = self.inputs.offs[j.rid]
                 desc[i] = (j.prime_id, j.size, j.size, 0, a0, b0, cpos)
                 cpos += 2 * j.size + 1
             plan = self.plans[slot]
+            t1 = clk()
             plan.update(desc, stream=s)
-        scr_words = (plan.scratch_bytes + 3) // 4 if plan is not None else 0
+            t_plan = clk() - t1
+        if one:
+            scr_words = (ntt.scratch_bytes(polys[0].size, polys[0].size) + 3) // 4
+        else:
+            scr_words = (plan.scratch_bytes + 3) // 4 if plan is not None else 0
         need = sum(_a4(j.size) for j in muls) + (_a4(cpos) + _a4(scr_words) if polys else 0)
         arena = self.arenas[slot] if need <= self.arena_words else None
         if arena is None:
@@ -360,20 +427,44 @@ class GpuBatchExecutor:
                 descs[i] = mont.VecDesc(base + 4 * a0, base + 4 * b0, out.data_ptr(), j.size, prm.P, prm.Pprime)
                 j.result = out
                 keep.append(out)
+            t1 = clk()
             self.vecb[slot].update_raw(descs, stream=s)
             self.vecb[slot].mul(stream=s)
-        if polys:
+            t_vec = clk() - t1
+        if one:
+            j = polys[0]
+            out = take(cpos)
+            scr = take(scr_words) if scr_words else None
+            a0, b0, _ = self.inputs.offs[j.rid]
+            base = self.inputs.arena.data_ptr()
+            t1 = clk()
+            mont.check(mont.lib().ntt_polymul(self.ctx.handle, j.prime_id, base + 4 * a0, j.size, base + 4 * b0, j.size,
+                                              out.data_ptr(), scr.data_ptr() if scr is not None else None,
+                                              4 * scr_words, s.cuda_stream), "ntt_polymul")
+            t_exec = clk() - t1
+            keep += [out] + ([scr] if scr is not None else [])
+            j.result = out
+        elif polys:
             out = take(cpos)
             scr = take(scr_words)
+            t1 = clk()
             plan.execute(self.inputs.arena, out, scr, spin_limit=self.spin_limit, stream=s)
             plan.status_async(scr, self._status_ptr + 4 * slot, stream=s)
+            t_exec = clk() - t1
             keep += [out, scr]
             for i, j in enumerate(polys):
                 c0 = int(desc["c_off"][i])
                 j.result = out[c0:c0 + 2 * j.size + 1]
         ev = torch.cuda.Event()
         ev.record(s)
-        return (ev, batch, keep, slot, arena is not None, bool(polys))
+        total = clk() - t0
+        if total > 1e-3:
+            rec = (min(j.rid for j in batch), round(t_plan, 6), round(t_vec, 6), round(t_exec, 6),
+                   round(total - t_plan - t_vec - t_exec, 6))
+            if plan is not None:
+                rec += (plan.update_times_us(),)     # inside the library: plan, wait, upload, all (us)
+            self.slow_launches.append(rec)
+        return (ev, batch, keep, slot, arena is not None, bool(polys) and not one)
 
     def poll(self, handle) -> bool:
         return handle[0].query()

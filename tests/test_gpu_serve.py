@@ -160,7 +160,9 @@ def test_serving_batches_exact_and_alone_equals_mix(mods, ctx):
     mix = {j.rid: host(j.result) for j in stats.jobs}
     for r in reqs:
         assert np.array_equal(mix[r.rid], oracle_result(inputs, r)), r.rid
-    # every request alone through the same executor gives the same bytes
+    # every request alone through the same executor gives the same bytes (a
+    # one-product batch takes the plain launches, a mixed one the persistent
+    # launch)
     for r in reqs[::5]:
         st = serve.Scheduler(ex, slots=3, budget_bytes=1 << 30).run(serve.jobs_from_requests([r]))
         assert st.jobs[0].status == serve.OK
@@ -261,7 +263,9 @@ def test_serving_executor_reports_device_timeouts(mods, ctx):
     for r in reqs:
         r.t_arrival = 0.0
     inputs = serve.DeviceInputs(reqs, PRIMES)
-    ex = serve.GpuBatchExecutor(ctx, inputs, slots=2, max_batch=4, spin_limit=1)
+    # every batch through the persistent launch (one-product batches would
+    # otherwise take the plain launches, which have no dependency waits)
+    ex = serve.GpuBatchExecutor(ctx, inputs, slots=2, max_batch=4, spin_limit=1, single_plain=False)
     st = serve.Scheduler(ex, slots=2, budget_bytes=1 << 32, max_batch=4).run(serve.jobs_from_requests(reqs))
     failed = [j for j in st.jobs if j.status == serve.FAILED]
     assert failed, "long products with a one-sleep wait bound should time out"
