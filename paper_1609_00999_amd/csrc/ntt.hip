@@ -77,17 +77,28 @@ struct ProdDev {
   uint32_t nblocks;         // row blocks (2^(n - 13))
   uint32_t nout;            // coefficients stored
   uint32_t to_scr;          // 1: c_off is an offset into the scratch buffer
-  uint32_t pad[3];
+  uint32_t tft;             // 0, or log2 N of the product whose truncated-transform block this is (below)
+  uint32_t pad[2];
 };
 
-// Fix-up of a product split into its cyclic part and its top part: with
-// h = 2^(n-1) and m = da + db + 1 - h, c[k] -= t[m-1+k] and c[h+k] = t[m-1+k]
-// for k < m, where t is the product of the top m coefficients of a and b.
+// Fix-up of a product computed in two parts, after the persistent launch.
+// Both kinds start from the cyclic part r = c mod (x^h - 1) in the output
+// (c[k] holds c_k + c_(h+k)), with h = 2^(n-1) and m = da + db + 1 - h.
+//  FIX_SPLIT: t is the product of the top m coefficients of a and b, and
+//    c[k] -= t[m-1+k], c[h+k] = t[m-1+k] for k < m.
+//  FIX_TFT: t is the truncated-transform block of length s (below), the
+//    cyclic product that gives u = c mod (x^s - w^s) as u_k = t_k w^-k, and
+//    q_k = (sum_i r_(k+is) w^(is) - u_k) / 2, c[k] -= q_k, c[h+k] = q_k for k < m.
+enum FixKind : uint32_t { FIX_SPLIT = 0, FIX_TFT = 1 };
 struct FixDev {
   uint64_t c_off;           // product output, in the output buffer
-  uint64_t t_off;           // top product, in the scratch buffer
+  uint64_t t_off;           // top product or block output, in the scratch buffer
   uint32_t m, h, P;
   uint32_t chunk0;          // first of its ceil(m / kFixChunk) chunks in the fix-up launch
+  uint32_t kind;            // FixKind
+  uint32_t prime_id;        // FIX_TFT: the prime (tables, Montgomery constants)
+  uint32_t s_log;           // FIX_TFT: log2 of the block length s
+  uint32_t pad;
 };
 constexpr uint32_t kFixChunk = 1024;
 // A reusable plan uploads products, fix-ups and tasks back to back in one block.
@@ -137,6 +148,33 @@ __host__ __device__ inline bool split_rule(uint32_t da, uint32_t db, int n, uint
   return nt <= n - 2;
 }
 
+// The two-block truncated transform (the truncated Fourier transform of the
+// paper's references, cut to two blocks).  A product of length L = da+db+1
+// in (N/2, N] is fixed by its residues modulo coprime factors of x^N - 1
+// whose degrees sum to at least L: here x^h - 1 (h = N/2, the cyclic part
+// above) and x^s - w^s with w = w_N and s = N/4 or N/8, whose roots are odd
+// powers of w.  The second residue is a cyclic product of length s of the
+// folded and twisted operands a'_r = w^r sum_i a_(r+is) w^(is) (likewise b'),
+// since a(w y) mod (y^s - 1) has exactly those coefficients; the fix-up
+// untwists it and joins both residues (Chinese remainders: (x^h - 1) =
+// -2 mod (x^s - w^s)).  For a product with N/16 < m <= N/4 (m = L - h) the
+// pair costs transforms of h + s points instead of N, and beats the split's
+// top product (>= 2m points).  Lengths from 2^18 keep the block at 2^15
+// points or more, where the column tiles read their first round from HBM
+// (the fold and twist happen in that load).
+constexpr int kTftMinLog = 18;
+
+__host__ __device__ inline bool tft_rule(uint32_t da, uint32_t db, int n, uint32_t& m, int& ls) {
+  if (n < kTftMinLog) return false;
+  const uint64_t N = 1ull << n, h = N >> 1;
+  if ((uint64_t)da + 1 > h || (uint64_t)db + 1 > h) return false;
+  const uint64_t mm = (uint64_t)da + db + 1 - h;
+  if (mm <= N / 16 || mm > N / 4) return false;
+  m = (uint32_t)mm;
+  ls = mm <= N / 8 ? n - 3 : n - 2;
+  return true;
+}
+
 __host__ __device__ inline uint32_t product_tasks(int n) {
   if (n <= kRowLog) return 1;
   const uint32_t ntiles = 1u << (kRowLog - col_lc(n));
@@ -149,7 +187,10 @@ __host__ __device__ inline uint32_t product_tasks(int n) {
 struct SlotShape {
   int err;                  // nonzero: the product's descriptor is invalid (a mont_status)
   bool used;
-  bool split;               // the product is split (both slots describe it)
+  bool split;               // the product is computed in two parts (both slots describe it)
+  bool tft;                 // ... as a cyclic part and a truncated-transform block (else a top product)
+  bool block;               // this slot is the truncated-transform block
+  int nfull;                // log2 N of the whole product
   int n;                    // log2 of the slot's transform length
   uint32_t da, db;          // the slot's operand degrees
   uint64_t a_off, b_off;    // the slot's operand offsets in the input
@@ -176,7 +217,9 @@ __host__ __device__ inline SlotShape slot_shape(const polymul_desc& d, int part,
   }
   uint32_t m = 0;
   int nt = 0;
-  sh.split = split_rule(d.da, d.db, n, m, nt);
+  sh.nfull = n;
+  sh.tft = tft_rule(d.da, d.db, n, m, nt);
+  sh.split = sh.tft || split_rule(d.da, d.db, n, m, nt);
   if (!sh.split) {
     sh.used = part == 0;
     sh.n = n;
@@ -198,6 +241,14 @@ __host__ __device__ inline SlotShape slot_shape(const polymul_desc& d, int part,
     sh.a_off = d.a_off;
     sh.b_off = d.b_off;
     sh.nout = h;
+  } else if (sh.tft) {          // block of length 2^nt: folds and twists the whole operands
+    sh.block = true;
+    sh.n = nt;
+    sh.da = d.da;
+    sh.db = d.db;
+    sh.a_off = d.a_off;
+    sh.b_off = d.b_off;
+    sh.nout = m;
   } else {                      // top part, into scratch
     sh.n = nt;
     sh.da = m - 1;
@@ -207,6 +258,28 @@ __host__ __device__ inline SlotShape slot_shape(const polymul_desc& d, int part,
     sh.nout = 2 * m - 1;
   }
   return sh;
+}
+
+// REDC operations a slot executes: three transforms of (N/2) log2 N
+// butterflies, N pointwise products and db + 1 scalings of b; a block also
+// folds (one product per operand coefficient beyond its length) and twists
+// (one per point, both operands).
+__host__ __device__ inline uint64_t slot_redc(const SlotShape& sh) {
+  const uint64_t N = 1ull << sh.n;
+  uint64_t r = 3 * (N / 2) * (uint64_t)sh.n + N + (sh.block ? N : (uint64_t)sh.db + 1);
+  if (sh.block) {
+    r += 2 * N;
+    r += sh.da + 1 > N ? sh.da + 1 - N : 0;
+    r += sh.db + 1 > N ? sh.db + 1 - N : 0;
+  }
+  return r;
+}
+
+// REDC operations of a product's fix-up, counted on its second slot: a
+// block's untwist, the fold of the cyclic part and the halving, per fixed
+// coefficient.
+__host__ __device__ inline uint64_t fix_redc(const SlotShape& sh) {
+  return sh.block ? (uint64_t)sh.m * ((sh.h >> sh.n) + 1) : 0;
 }
 
 // Scratch words a slot's data take: the two length-N transforms of a
@@ -493,6 +566,12 @@ struct ColIO {
   uint32_t scale;        // first round: nonzero multiplies by REDC(x * scale)
   uint32_t* dst;         // last round: stores only indices < nout
   uint32_t nout;
+  // A truncated-transform block (forward tiles): the first round loads
+  // w^r sum_i src[r + i s] w^(is) instead of src[r], with s the tile's
+  // transform length and w = w_N of the whole product.
+  const uint32_t* twist; // nullptr: plain load; else entry r holds w^r (Montgomery form)
+  uint32_t fold_s;       // s
+  uint32_t z[3];         // w^(is) for i = 1, 2, 3 (Montgomery form; 0 where unused)
 };
 
 // One round with compile-time geometry: rows of 2^LC columns (LC = 0 for the
@@ -536,10 +615,25 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
       const uint32_t gi0 = colbase + c + ((base >> LC) << RS);
       constexpr int GS = S_LO + RS;
       if constexpr (GIN) {
+        if (io.twist) {
+          // fold modulo x^s - w^s (operands are shorter than 4s), then twist
 #pragma unroll
-        for (int j = 0; j < E; j++) {
-          const uint32_t gi = gi0 + ((uint32_t)j << GS);
-          v[j] = gi <= io.dvalid ? io.src[gi] : 0u;
+          for (int j = 0; j < E; j++) {
+            const uint32_t gi = gi0 + ((uint32_t)j << GS);
+            uint32_t acc = gi <= io.dvalid ? io.src[gi] : 0u;
+#pragma unroll
+            for (int i = 1; i < 4; i++) {
+              const uint32_t gk = gi + (uint32_t)i * io.fold_s;
+              if (gk <= io.dvalid) acc = madd(acc, mmul(io.src[gk], io.z[i - 1], md), md.P);
+            }
+            v[j] = mmul(acc, ldg(io.twist, gi), md);
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < E; j++) {
+            const uint32_t gi = gi0 + ((uint32_t)j << GS);
+            v[j] = gi <= io.dvalid ? io.src[gi] : 0u;
+          }
         }
         if (io.scale) {
 #pragma unroll
@@ -770,15 +864,26 @@ __device__ __forceinline__ void exec_small_poly(const PrimeDev& pr, int n, const
 
 // Forward column pass, tile t: rows k < 2^n1, columns t*C + c; the input is
 // zero beyond index dvalid; scale != 0 multiplies by REDC(x * scale) on load.
+// A truncated-transform block (tft = log2 N of the whole product, 0 for a
+// plain product; lengths 2^15 and up) folds and twists its operand in the
+// first round's loads.
 template <int NT, int RM, bool COH>
 __device__ __forceinline__ void exec_col_dif(const PrimeDev& pr, int n, int lc, uint32_t t, const uint32_t* src, uint32_t dvalid,
-                             uint32_t scale, uint32_t* dst, uint32_t* X) {
+                             uint32_t scale, uint32_t* dst, uint32_t* X, uint32_t tft = 0) {
   const Mod md = mod_of(pr);
   const int n1 = n - kRowLog;
   const uint32_t colbase = t << lc;
   const uint32_t cnt = 1u << (n1 + lc);
   const uint32_t cmask = (1u << lc) - 1;
-  if (col_fixed<NT, RM, false, COH>(n, X, colbase, pr.twf, md, ColIO{src, dvalid, scale, dst, 0xFFFFFFFFu})) return;
+  ColIO io = ColIO{src, dvalid, scale, dst, 0xFFFFFFFFu};
+  if (tft) {
+    const uint32_t half = 1u << (tft - 1);        // w^r for r < N/2 sits at table entry N/2 + r
+    io.twist = pr.twf + half;
+    io.fold_s = 1u << n;
+#pragma unroll
+    for (int i = 1; i < 4; i++) io.z[i - 1] = (uint32_t)i << n < half ? ldg(pr.twf, half + ((uint32_t)i << n)) : 0u;
+  }
+  if (col_fixed<NT, RM, false, COH>(n, X, colbase, pr.twf, md, io)) return;
   if (lc >= 2 && ((uintptr_t)src & 15u) == 0) {
     // rows of C >= 4 adjacent residues: 128-bit loads where all four are
     // inside the operand, element loads on the (at most one) straddling chunk
@@ -1039,13 +1144,20 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
   const uint32_t S = 1u << kRowLog;
   // written by the planning kernel before this launch (zero after a planning error)
   const uint32_t ntasks = g.dyn ? g.scr[kHdrNtasks] : g.ntasks;
+  if (threadIdx.x == 0) s_task = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (;;) {
-    if (threadIdx.x == 0) s_task = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     // uniform across the workgroup: keeps the task's fields and pointers in
     // scalar registers
     const uint32_t ti = __builtin_amdgcn_readfirstlane(s_task);
     if (ti >= ntasks) break;
+    // Reserve the next task now: its index is needed only when this task
+    // ends, so the atomic's round trip overlaps the work.  A workgroup holds
+    // at most one reserved task beside its running one, and the lowest
+    // unfinished task is always a running one (a reserved task's workgroup
+    // is busy with a lower one), so every wait still ends.
+    uint32_t next = 0;
+    if (threadIdx.x == 0) next = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint2 tk = g.inl ? g.inl_tasks[ti] : g.tasks[ti];
     const uint32_t p = tk.x;
     const uint32_t kind = tk.y >> 28;
@@ -1067,9 +1179,9 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
           exec_small_poly<NT, RM>(pr, pd.n, g.in + pd.a_off, pd.da, g.in + pd.b_off, pd.db,
                                   (pd.to_scr ? g.scr : g.out) + pd.c_off, pd.nout, X);
           break;
-        case T_COLF_A: exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X); break;
+        case T_COLF_A: exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.a_off, pd.da, 0u, scr, X, pd.tft); break;
         case T_COLF_B:
-          exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X);
+          exec_col_dif<NT, RM, true>(pr, pd.n, pd.lc, idx, g.in + pd.b_off, pd.db, pr.s2[pd.n], scr + N, X, pd.tft);
           break;
         case T_ROW: exec_row<NT, RM, true>(pr, kRowLog, ROW_POLY, scr + idx * S, scr + N + idx * S, 0u, X); break;
         default:
@@ -1088,6 +1200,7 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) s_task = next;
   }
 }
 
@@ -1099,8 +1212,9 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
 // A batch planned on the device passes dyn_nchunks, its header word holding
 // the chunk count (its records of unsplit products have m = 0 and are never
 // selected: each shares its first chunk index with a later record).
-__global__ __launch_bounds__(256) void k_split_fix(const FixDev* fx, uint32_t nfix, uint32_t nchunks, uint32_t* out,
-                                                   const uint32_t* scr, const uint32_t* dyn_nchunks) {
+__global__ __launch_bounds__(256) void k_split_fix(const PrimeDev* primes, const FixDev* fx, uint32_t nfix,
+                                                   uint32_t nchunks, uint32_t* out, const uint32_t* scr,
+                                                   const uint32_t* dyn_nchunks) {
   if (dyn_nchunks) nchunks = *dyn_nchunks;
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
     uint32_t lo = 0, hi = nfix;                  // fx[lo].chunk0 <= c < fx[hi].chunk0
@@ -1111,13 +1225,52 @@ __global__ __launch_bounds__(256) void k_split_fix(const FixDev* fx, uint32_t nf
     }
     const FixDev d = fx[lo];
     uint32_t* cc = out + d.c_off;
-    const uint32_t* t = scr + d.t_off + (d.m - 1);
     const uint32_t k0 = (c - d.chunk0) * kFixChunk;
     const uint32_t k1 = min(d.m, k0 + kFixChunk);
-    for (uint32_t k = k0 + threadIdx.x; k < k1; k += 256) {
-      const uint32_t hv = t[k];
-      cc[k] = msub(cc[k], hv, d.P);
-      cc[d.h + k] = hv;
+    if (d.kind == FIX_TFT) {
+      // Block output t (m words) and cyclic part r = cc[0 .. h).  Indices k
+      // < m <= s are rewritten; the fold reads r at k + i s >= s only.
+      const PrimeDev& pr = primes[d.prime_id];
+      const Mod md{pr.P, pr.Pp};
+      const uint32_t sl = d.s_log, nf = d.h >> sl;           // 2 or 4 terms fold r modulo x^s - w^s
+      const uint32_t* t = scr + d.t_off;
+      uint32_t z[3];
+#pragma unroll
+      for (int i = 1; i < 4; i++) z[i - 1] = (uint32_t)i < nf ? ldg(pr.twf, d.h + ((uint32_t)i << sl)) : 0u;
+      const uint32_t half = (pr.R1 & 1u ? pr.R1 + pr.P : pr.R1) >> 1;    // R / 2 mod P: REDC(x half) = x / 2
+      // Each lane takes four coefficients of the chunk and issues all their
+      // loads before any arithmetic, so the loads' latencies overlap.
+      constexpr int kPer = kFixChunk / 256;
+      uint32_t tv[kPer], wv[kPer], rv[kPer][4];
+#pragma unroll
+      for (int j = 0; j < kPer; j++) {
+        const uint32_t k = k0 + threadIdx.x + 256u * j;
+        const bool in = k < k1;
+        tv[j] = in ? t[k] : 0u;
+        wv[j] = in ? ldg(pr.twi, d.h + k) : 0u;
+#pragma unroll
+        for (uint32_t i = 0; i < 4; i++) rv[j][i] = in && i < nf ? cc[k + (i << sl)] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < kPer; j++) {
+        const uint32_t k = k0 + threadIdx.x + 256u * j;
+        if (k >= k1) continue;
+        const uint32_t u = mmul(tv[j], wv[j], md);                     // t_k w^-k
+        uint32_t f = rv[j][0];
+#pragma unroll
+        for (uint32_t i = 1; i < 4; i++)
+          if (i < nf) f = madd(f, mmul(rv[j][i], z[i - 1], md), md.P);
+        const uint32_t q = mmul(msub(f, u, md.P), half, md);
+        cc[k] = msub(rv[j][0], q, md.P);
+        cc[d.h + k] = q;
+      }
+    } else {
+      const uint32_t* t = scr + d.t_off + (d.m - 1);
+      for (uint32_t k = k0 + threadIdx.x; k < k1; k += 256) {
+        const uint32_t hv = t[k];
+        cc[k] = msub(cc[k], hv, d.P);
+        cc[d.h + k] = hv;
+      }
     }
   }
 }
@@ -1319,6 +1472,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
         pd.b_off = sh.b_off;
         pd.nout = sh.nout;
         pd.to_scr = sh.split && part == 1 ? 1u : 0u;
+        pd.tft = sh.block ? (uint32_t)sh.nfull : 0u;
         pd.c_off = pd.to_scr ? dat + (sh.n > kRowLog ? (2ull << sh.n) : 0ull) : d.c_off;
         uint32_t nt = 0, nb = 0;
         if (sh.n > kRowLog) {
@@ -1347,13 +1501,16 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
       // one fix-up record per product: the top slot writes a split product's,
       // slot 2i an unsplit one's (m = 0, never selected)
       if (sh.split && part == 1) {
-        FixDev f;
+        FixDev f = {};
         f.c_off = d.c_off;
         f.t_off = dat + (sh.n > kRowLog ? (2ull << sh.n) : 0ull);
         f.m = sh.m;
         f.h = sh.h;
         f.P = primes[d.prime_id].P;
         f.chunk0 = chunk0;
+        f.kind = sh.block ? FIX_TFT : FIX_SPLIT;
+        f.prime_id = d.prime_id;
+        f.s_log = (uint32_t)sh.n;
         fixes[slot >> 1] = f;
       } else if (!sh.split && part == 0) {
         FixDev f = {};
@@ -1918,60 +2075,51 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   std::vector<uint2> small;
   in_words = 0;
   out_words = 0;
-  std::vector<uint32_t> top_words;                 // per fix-up: words of its top output
+  std::vector<uint32_t> top_words;                 // per fix-up: words of its second part's output
+  const uint32_t nprimes = (uint32_t)ctx->params.size();
   for (int p = 0; p < count; p++) {
     const polymul_desc& d = descs[p];
-    if (d.prime_id >= ctx->params.size() || d.reserved != 0) return MONT_EINVAL;
-    uint64_t nout = (uint64_t)d.da + d.db + 1;
-    if (nout > ((uint64_t)1 << 31)) return MONT_ERANGE;
-    int n = ceil_log2(nout);
-    if ((uint32_t)n > ctx->logmax[d.prime_id]) return MONT_ENOROOT;
+    const SlotShape s0 = slot_shape(d, 0, nprimes, ctx->logmax.data());
+    if (s0.err) return s0.err;
+    const uint64_t nout = (uint64_t)d.da + d.db + 1;
     in_words = std::max<uint64_t>(in_words, std::max(d.a_off + d.da + 1, d.b_off + d.db + 1));
     out_words = std::max<uint64_t>(out_words, d.c_off + nout);
-    ProdDev pd;
-    std::memset(&pd, 0, sizeof(pd));
-    pd.prime_id = d.prime_id;
-    pd.da = d.da;
-    pd.db = d.db;
-    pd.a_off = d.a_off;
-    pd.b_off = d.b_off;
-    pd.c_off = d.c_off;
-    uint32_t m = 0;
-    int nt = 0;
-    if (split_rule(d.da, d.db, n, m, nt)) {
-      const uint32_t h = 1u << (n - 1);
-      pd.n = (uint32_t)(n - 1);                    // cyclic part, straight into the output
-      pd.nout = h;
+    for (int part = 0; part < 2; part++) {
+      const SlotShape sh = part == 0 ? s0 : slot_shape(d, 1, nprimes, ctx->logmax.data());
+      if (!sh.used) continue;
+      ProdDev pd;
+      std::memset(&pd, 0, sizeof(pd));
+      pd.prime_id = d.prime_id;
+      pd.n = (uint32_t)sh.n;
+      pd.da = sh.da;
+      pd.db = sh.db;
+      pd.a_off = sh.a_off;
+      pd.b_off = sh.b_off;
+      pd.c_off = d.c_off;                          // second parts: set with the scratch layout
+      pd.nout = sh.nout;
+      pd.to_scr = part == 1 ? 1u : 0u;
+      pd.tft = sh.block ? (uint32_t)sh.nfull : 0u;
       prods.push_back(pd);
-      ProdDev tp = pd;                             // top part, into scratch
-      tp.n = (uint32_t)nt;
-      tp.da = m - 1;
-      tp.db = m - 1;
-      tp.a_off = d.a_off + (h - d.db);
-      tp.b_off = d.b_off + (h - d.da);
-      tp.nout = 2 * m - 1;
-      tp.to_scr = 1;
-      prods.push_back(tp);
-      FixDev f;
-      f.c_off = d.c_off;
-      f.t_off = 0;                                 // set with the scratch layout
-      f.m = m;
-      f.h = h;
-      f.P = ctx->params[d.prime_id].P;
-      f.chunk0 = nchunks;
-      nchunks += (m + kFixChunk - 1) / kFixChunk;
-      fixes.push_back(f);
-      top_words.push_back(2 * m - 1);
-    } else {
-      pd.n = (uint32_t)n;
-      pd.nout = (uint32_t)nout;
-      prods.push_back(pd);
+      redc += slot_redc(sh) + fix_redc(sh);
+      if (part == 1) {
+        FixDev f;
+        std::memset(&f, 0, sizeof(f));
+        f.c_off = d.c_off;
+        f.t_off = 0;                               // set with the scratch layout
+        f.m = sh.m;
+        f.h = sh.h;
+        f.P = ctx->params[d.prime_id].P;
+        f.chunk0 = nchunks;
+        f.kind = sh.block ? FIX_TFT : FIX_SPLIT;
+        f.prime_id = d.prime_id;
+        f.s_log = (uint32_t)sh.n;
+        nchunks += (sh.m + kFixChunk - 1) / kFixChunk;
+        fixes.push_back(f);
+        top_words.push_back(sh.nout);
+      }
     }
   }
   const int np = (int)prods.size();
-  // Executed REDC: three transforms of (N/2) n butterflies, N pointwise
-  // products and db + 1 scalings of b per internal product.
-  for (const ProdDev& pd : prods) redc += 3ull * (1ull << pd.n) / 2 * pd.n + (1ull << pd.n) + pd.db + 1;
   uint64_t scr = kHdrWords + 2ull * np;
   scr = (scr + 63) & ~63ull;
   for (int p = 0, f = 0; p < np; p++) {
@@ -2250,12 +2398,18 @@ extern "C" mont_status ntt_plan_update_times(const ntt_plan* plan, uint32_t* us)
 }
 
 extern "C" uint32_t ntt_plan_task_count(uint32_t da, uint32_t db) {
-  if ((uint64_t)da + db + 1 > ((uint64_t)1 << 31)) return 0;
-  const int n = ceil_log2((uint64_t)da + db + 1);
-  uint32_t m = 0;
-  int nt = 0;
-  if (split_rule(da, db, n, m, nt)) return product_tasks(n - 1) + product_tasks(nt);
-  return product_tasks(n);
+  polymul_desc d;
+  std::memset(&d, 0, sizeof(d));
+  d.da = da;
+  d.db = db;
+  const uint32_t any_length = 31;                   // the rules do not depend on the prime
+  uint32_t t = 0;
+  for (int part = 0; part < 2; part++) {
+    const SlotShape sh = slot_shape(d, part, 1, &any_length);
+    if (sh.err) return 0;
+    if (sh.used) t += product_tasks(sh.n);
+  }
+  return t;
 }
 
 extern "C" mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, uint32_t* ntasks,
@@ -2310,8 +2464,9 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   gsz = std::max(1u, std::min(gsz, plan->ntasks));
   launch_persistent(g, gsz, s);
   if (plan->nfix > 0)
-    hipLaunchKernelGGL(k_split_fix, dim3(std::min(plan->nchunks, 8192u)), dim3(256), 0, s, plan->d_fix, plan->nfix,
-                       plan->nchunks, d_out, static_cast<const uint32_t*>(scr), nullptr);
+    // one workgroup per chunk: the chunks' record searches run in parallel
+    hipLaunchKernelGGL(k_split_fix, dim3(plan->nchunks), dim3(256), 0, s, plan->ctx->d_primes,
+                       plan->d_fix, plan->nfix, plan->nchunks, d_out, static_cast<const uint32_t*>(scr), nullptr);
   return last_launch_status();
 }
 
@@ -2383,8 +2538,11 @@ extern "C" mont_status ntt_polymul_batch(const ntt_ctx* ctx, const polymul_desc*
   g.spin_limit = 1u << 24;
   g.dyn = 1;
   launch_persistent(g, (uint32_t)persistent_grid(), s);
-  hipLaunchKernelGGL(k_split_fix, dim3(1024), dim3(256), 0, s, reinterpret_cast<const FixDev*>(scr + lay.fixes),
-                     (uint32_t)count, 0u, d_out, static_cast<const uint32_t*>(scr), scr + kHdrNchunks);
+  // the chunk count is known only on the device: a grid that covers the
+  // chunks of most batches at one workgroup each, striding beyond
+  hipLaunchKernelGGL(k_split_fix, dim3(32768), dim3(256), 0, s, ctx->d_primes,
+                     reinterpret_cast<const FixDev*>(scr + lay.fixes), (uint32_t)count, 0u, d_out,
+                     static_cast<const uint32_t*>(scr), scr + kHdrNchunks);
   return last_launch_status();
 }
 

@@ -338,9 +338,11 @@ def test_batch_longest_lengths(N, ctx):
     """One persistent launch holding unsplit products of transform lengths
     2^22 and 2^23 (the longest compile-time column tiles) beside short ones:
     every coefficient against the oracle."""
-    # none of these meets the split rule: the top product would be longer than N/4
-    da = np.array([1500000, (1 << 22) - 1, (1 << 21) - 1, 3000, 120000, 14000], dtype=np.int64)
-    db = np.array([1500000, (1 << 22) - 1, 1 << 20, 2000, 120000, 14100], dtype=np.int64)
+    # none of these is computed in two parts: each length lies above 3N/4
+    # (no truncated-transform block) and its top product would be longer
+    # than N/4 (no split)
+    da = np.array([1600000, (1 << 22) - 1, (1 << 21) - 1, 3000, 120000, 14000], dtype=np.int64)
+    db = np.array([1600000, (1 << 22) - 1, (1 << 20) + 10, 2000, 120000, 14100], dtype=np.int64)
     rng = np.random.default_rng(2223)
     pid = rng.integers(0, len(PRIMES), da.size)
     batch = wl.pack_products(PRIMES, pid, da, db, rng)
@@ -441,6 +443,13 @@ SPLIT_SHAPES = [(1, 1), (2, 1), (2, 2), (4, 4), (16, 16), (32, 31), (33, 30), (6
                 (9000, 9100), (20000, 20000), (40000, 30000), (70000, 70000), (65600, 65400),
                 ((1 << 19) + 3, (1 << 19) + 1), ((1 << 20) + 100, (1 << 20) - 100), (300000, 900)]
 
+# Shapes the two-block truncated transform takes (N >= 2^18, both operands
+# below h = N/2, N/16 < m = L - h <= N/4): block of N/8 points for m <= N/8,
+# of N/4 above; unbalanced operands fold four terms.  Edges of each range.
+TFT_SHAPES = [(75535, 75535), (81919, 65537), (73728, 73728), (90111, 90112), (98303, 98304),
+              (131071, 32768), (700000, 700000), (1000000, 200000), (1048575, 262144), (600000, 600000),
+              (4000000, 2000000), (3000000, 2000000), ((1 << 21) + 1, (1 << 21) + 1), (2621440, 2621440)]
+
 
 def test_split_rule_is_used(N):
     """The plan splits products just above a power of two (fewer tasks than
@@ -505,33 +514,83 @@ def test_split_special_values(N, ctx):
         assert all(int(got[i]) == c2[int(i)] for i in idx)
 
 
-def test_plan_work_counts(N, ctx):
-    """ntt_plan_work reports the REDC of the products as planned: the split
-    rule (multi-pass product, both operands below h = N/2, top product of
-    length <= N/4) restated here, and three transforms, N pointwise products
-    and db+1 scalings per planned product."""
-    def cost(n, db):
-        return 3 * (1 << n) // 2 * n + (1 << n) + db + 1
+def planned_work(da, db):
+    """The planning rules restated: (executed REDC, 1 if computed in two
+    parts).  Two-block truncated transform when N >= 2^18, both operands
+    below h = N/2 and N/16 < m = L - h <= N/4 (block of N/8 points for m <=
+    N/8, N/4 above); otherwise the split when the product is multi-pass, both
+    operands are below h and the top product's length 2^nt >= 2m - 1 is at
+    most N/4; otherwise whole.  A product costs three transforms, N pointwise
+    products and db+1 scalings; a block scales all its N points and adds its
+    fold and twist products, and its fix-up m (h/s + 1)."""
+    def cost(n, dbb):
+        return 3 * (1 << n) // 2 * n + (1 << n) + dbb + 1
 
+    L = da + db + 1
+    n = (L - 1).bit_length()
+    N, h = 1 << n, 1 << max(n - 1, 0)
+    m = L - h
+    if n >= 18 and da + 1 <= h and db + 1 <= h and N // 16 < m <= N // 4:
+        ls = n - 3 if m <= N // 8 else n - 2
+        S = 1 << ls
+        block = cost(ls, S - 1) + 2 * S + max(0, da + 1 - S) + max(0, db + 1 - S)
+        return cost(n - 1, db) + block + m * (h // S + 1), 1
+    if n > 13 and da + 1 <= h and db + 1 <= h and (2 * m - 2).bit_length() <= n - 2:
+        return cost(n - 1, db) + cost((2 * m - 2).bit_length(), m - 1), 1
+    return cost(n, db), 0
+
+
+def test_plan_work_counts(N, ctx):
+    """ntt_plan_work reports the REDC of the products as planned (rules above)."""
     rng = np.random.default_rng(5)
-    da = [s[0] for s in SPLIT_SHAPES]
-    db = [s[1] for s in SPLIT_SHAPES]
+    shapes = SPLIT_SHAPES + TFT_SHAPES
+    da = [s[0] for s in shapes]
+    db = [s[1] for s in shapes]
     batch = wl.pack_products(PRIMES, rng.integers(0, len(PRIMES), len(da)), da, db, rng)
     want, nsplit = 0, 0
     for a, b in zip(da, db):
-        L = a + b + 1
-        n = (L - 1).bit_length()
-        h = 1 << (n - 1)
-        m = L - h
-        if n > 13 and a + 1 <= h and b + 1 <= h and (2 * m - 2).bit_length() <= n - 2:
-            want += cost(n - 1, b) + cost((2 * m - 2).bit_length(), m - 1)
-            nsplit += 1
-        else:
-            want += cost(n, b)
+        w, sp = planned_work(a, b)
+        want += w
+        nsplit += sp
     plan = N.Plan.from_batch(ctx, batch)
     assert plan.work() == (want, nsplit)
     assert nsplit > 0
     plan.close()
+
+
+def test_truncated_transform_shapes_vs_oracle(N, ctx):
+    """Products the two-block truncated transform takes, at the edges of its
+    ranges, with balanced and unbalanced operands: every coefficient against
+    the oracle, in the persistent plan (two grids and a shuffled order) and
+    through the one-call batch."""
+    for sh in TFT_SHAPES:
+        assert planned_work(*sh)[1] == 1 and N.task_count(*sh) < N.task_count(sh[0] + sh[1], 0)
+    rng = np.random.default_rng(78)
+    batch = wl.pack_products(PRIMES, rng.integers(0, len(PRIMES), len(TFT_SHAPES)),
+                             [x[0] for x in TFT_SHAPES], [x[1] for x in TFT_SHAPES], rng)
+    outs = []
+    for grid, seed in [(0, 0), (5, 4242)]:
+        st, got = run_plan(N, ctx, batch, grid=grid, order_seed=seed)
+        assert st == 0
+        outs.append(got)
+    assert_batch_exact(batch, outs[0])
+    assert outs[0].tobytes() == outs[1].tobytes()
+    st, one = run_one_call(N, ctx, batch)
+    assert st == 0 and one[:batch.out_len].tobytes() == outs[0].tobytes()
+
+
+def test_truncated_transform_special_values(N, ctx):
+    """All-(P-1) operands (the largest residues everywhere the folds add) at
+    block lengths N/8 and N/4: c_k = min(k, 2d - k) + 1."""
+    for d in (75535, 98303, 700000):
+        P = PRIMES[d % len(PRIMES)]
+        b = wl.pack_products(PRIMES, [PRIMES.index(P)], [d], [d], np.random.default_rng(0))
+        b.coeffs[b.a_off[0]:b.a_off[0] + d + 1] = P - 1
+        b.coeffs[b.b_off[0]:b.b_off[0] + d + 1] = P - 1
+        st, got = run_plan(N, ctx, b)
+        assert st == 0
+        k = np.arange(2 * d + 1, dtype=np.int64)
+        assert np.array_equal(got[:2 * d + 1].astype(np.int64), (np.minimum(k, 2 * d - k) + 1) % P)
 
 
 # ---------------------------------------------------------------------------
