@@ -279,6 +279,19 @@ MONT_API mont_status ntt_batch_status(const void* d_scratch, void* stream);
 MONT_API mont_status ntt_tune_set(int threads, int radix_log, int grid_mult);
 MONT_API mont_status ntt_tune_get(int* threads, int* radix_log, int* grid_mult);
 
+/*
+ * Per-length launch shapes (the autotuner's per-length buckets): the shape
+ * for transforms of length 2^log2n (log2n in [0, 23]).  Plain launches
+ * (ntt_forward, ntt_inverse, ntt_polymul and its variants) use the shape of
+ * their length; a plan takes, when it is created or updated, the shape of
+ * the length that carries at least 90 % of its butterflies, or else the
+ * default of ntt_tune_set; ntt_polymul_batch uses that default.  threads == 0 removes the entry (the default
+ * applies again).  ntt_tune_get_length reports the shape in force for the
+ * length.  Never changes results.  Errors: MONT_EINVAL.
+ */
+MONT_API mont_status ntt_tune_set_length(int log2n, int threads, int radix_log, int grid_mult);
+MONT_API mont_status ntt_tune_get_length(int log2n, int* threads, int* radix_log, int* grid_mult);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1651,6 +1651,17 @@ mont_status noalloc_scratch_on(int device, uint32_t** out) {
 
 }  // namespace
 
+namespace mont {
+// Launch shape of the transform kernels: threads per workgroup, the largest
+// radix-2^R round, and the persistent grid as a multiple of the resident
+// workgroups.
+struct NttTune {
+  int threads;
+  int radix_log;
+  int grid_mult;
+};
+}  // namespace mont
+
 struct ntt_ctx {
   int device = 0;
   int log2_nmax = 0;
@@ -1693,6 +1704,7 @@ struct ntt_plan {
   bool inl = false;
   ProdDev inl_prods[kInlineProds];
   uint2 inl_tasks[kInlineTasks];
+  NttTune shape = {512, 4, 1};  // launch shape, chosen when the plan is (re)planned
   // host time of the last ntt_plan_update, microseconds: planning, waiting
   // for the previous upload to leave staging, the upload call, in all
   uint32_t upd_us[4] = {0, 0, 0, 0};
@@ -1702,14 +1714,40 @@ namespace {
 
 mont_status hip_ok(hipError_t e) { return e == hipSuccess ? MONT_OK : MONT_EHIP; }
 
-// Launch shape of the transform kernels: threads per workgroup and the
-// largest radix-2^R round.  Process-wide; read when a launch is enqueued.
-struct NttTune {
-  int threads;
-  int radix_log;
-  int grid_mult;   // persistent grid = resident workgroups x grid_mult
-};
+// Launch shapes: the process-wide default, and per transform length
+// (threads == 0: no entry, the default applies).  Read when a launch is
+// enqueued, and for a plan when it is (re)planned.
 NttTune g_ntt_tune = {512, 4, 1};
+NttTune g_ntt_len[kMaxLog + 1] = {};
+
+NttTune shape_for(int n) {
+  const NttTune& e = g_ntt_len[n < 0 ? 0 : (n > kMaxLog ? kMaxLog : n)];
+  return e.threads ? e : g_ntt_tune;
+}
+
+bool shape_ok(int threads, int radix_log, int grid_mult) {
+  return (threads == 256 || threads == 512 || threads == 1024) && (radix_log == 3 || radix_log == 4) &&
+         (grid_mult == 1 || grid_mult == 2 || grid_mult == 4);
+}
+
+// A plan's launch shape.  A plan with at least 90 % of its butterflies
+// (2^n n per product of length 2^n) at one transform length takes that
+// length's shape (a batch of one length, like most of a serving loop's);
+// any other takes the default, which the tuner picks on a batch of uneven
+// lengths (on MI355X the two differ: 1024-thread workgroups win on batches
+// of one length, 512-thread ones on the uneven 2048-product batch).
+NttTune plan_shape(const std::vector<ProdDev>& prods) {
+  double work[kMaxLog + 1] = {}, total = 0;
+  for (const ProdDev& pd : prods) {
+    const double w = std::ldexp((double)pd.n + 1, (int)pd.n);
+    work[pd.n] += w;
+    total += w;
+  }
+  int best = 0;
+  for (int n = 1; n <= kMaxLog; n++)
+    if (work[n] > work[best]) best = n;
+  return total > 0 && work[best] >= 0.9 * total ? shape_for(best) : g_ntt_tune;
+}
 
 template <int NT, int RM>
 void launch_direct_v(const DirectArgs& g, uint32_t grid, hipStream_t s) {
@@ -1732,9 +1770,11 @@ int occupancy_v() {
 
 #define MONT_NTT_VARIANTS(X) X(256, 3) X(256, 4) X(512, 3) X(512, 4) X(1024, 3) X(1024, 4)
 
+// Plain launches take the shape of their transform length.
 void launch_direct(const DirectArgs& g, uint32_t grid, hipStream_t s) {
+  const NttTune sh = shape_for((int)g.n);
 #define MONT_V(T, R)                                                      \
-  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) {             \
+  if (sh.threads == T && sh.radix_log == R) {                             \
     launch_direct_v<T, R>(g, grid, s);                                    \
     return;                                                               \
   }
@@ -1743,9 +1783,9 @@ void launch_direct(const DirectArgs& g, uint32_t grid, hipStream_t s) {
   launch_direct_v<512, 4>(g, grid, s);
 }
 
-void launch_persistent(const PlanArgs& g, uint32_t grid, hipStream_t s) {
+void launch_persistent(const PlanArgs& g, uint32_t grid, hipStream_t s, const NttTune& sh) {
 #define MONT_V(T, R)                                                      \
-  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) {             \
+  if (sh.threads == T && sh.radix_log == R) {                             \
     launch_persistent_v<T, R>(g, grid, s);                                \
     return;                                                               \
   }
@@ -1761,12 +1801,12 @@ void launch_persistent(const PlanArgs& g, uint32_t grid, hipStream_t s) {
 constexpr int kGridDevices = 64;
 std::atomic<int> g_grid_cache[kGridDevices][6];
 
-int persistent_grid() {
+int persistent_grid(const NttTune& sh) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   int v = 0, per_cu = 1;
 #define MONT_V(T, R)                                                    \
-  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) break;     \
+  if (sh.threads == T && sh.radix_log == R) break;                     \
   v++;
   do {
     MONT_NTT_VARIANTS(MONT_V)
@@ -1779,13 +1819,13 @@ int persistent_grid() {
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
 #define MONT_V(T, R) \
-  if (g_ntt_tune.threads == T && g_ntt_tune.radix_log == R) per_cu = occupancy_v<T, R>();
+  if (sh.threads == T && sh.radix_log == R) per_cu = occupancy_v<T, R>();
     MONT_NTT_VARIANTS(MONT_V)
 #undef MONT_V
     resident = cus * per_cu;
     if (slot) slot->store(resident, std::memory_order_relaxed);
   }
-  return resident * g_ntt_tune.grid_mult;
+  return resident * sh.grid_mult;
 }
 
 bool prime_ok(const ntt_ctx* ctx, int prime_id) {
@@ -1808,10 +1848,28 @@ DirectArgs direct_base(const ntt_ctx* ctx, int prime_id, int n) {
 }  // namespace
 
 extern "C" mont_status ntt_tune_set(int threads, int radix_log, int grid_mult) {
-  if ((threads != 256 && threads != 512 && threads != 1024) || (radix_log != 3 && radix_log != 4) ||
-      (grid_mult != 1 && grid_mult != 2 && grid_mult != 4))
-    return MONT_EINVAL;
+  if (!shape_ok(threads, radix_log, grid_mult)) return MONT_EINVAL;
   g_ntt_tune = NttTune{threads, radix_log, grid_mult};
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_tune_set_length(int log2n, int threads, int radix_log, int grid_mult) {
+  if (log2n < 0 || log2n > kMaxLog) return MONT_EINVAL;
+  if (threads == 0) {
+    g_ntt_len[log2n] = NttTune{0, 0, 0};
+    return MONT_OK;
+  }
+  if (!shape_ok(threads, radix_log, grid_mult)) return MONT_EINVAL;
+  g_ntt_len[log2n] = NttTune{threads, radix_log, grid_mult};
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_tune_get_length(int log2n, int* threads, int* radix_log, int* grid_mult) {
+  if (log2n < 0 || log2n > kMaxLog || !threads || !radix_log || !grid_mult) return MONT_EINVAL;
+  const NttTune sh = shape_for(log2n);
+  *threads = sh.threads;
+  *radix_log = sh.radix_log;
+  *grid_mult = sh.grid_mult;
   return MONT_OK;
 }
 
@@ -2301,7 +2359,8 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
       return MONT_EHIP;
     }
   }
-  plan->default_grid = persistent_grid();
+  plan->shape = plan_shape(prods);
+  plan->default_grid = persistent_grid(plan->shape);
   *out = plan;
   return MONT_OK;
 }
@@ -2322,7 +2381,8 @@ extern "C" mont_status ntt_plan_reserve(const ntt_ctx* ctx, int max_products, ui
     free_plan(plan);
     return MONT_ENOMEM;
   }
-  plan->default_grid = persistent_grid();
+  plan->shape = g_ntt_tune;
+  plan->default_grid = persistent_grid(plan->shape);
   *out = plan;
   return MONT_OK;
 }
@@ -2387,6 +2447,8 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
+  plan->shape = plan_shape(prods);
+  plan->default_grid = persistent_grid(plan->shape);
   plan->upd_us[3] = us_since(t0);
   return MONT_OK;
 }
@@ -2419,7 +2481,7 @@ extern "C" mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes
   if (ntasks) *ntasks = plan->ntasks;
   if (in_words) *in_words = plan->in_words;
   if (out_words) *out_words = plan->out_words;
-  if (default_grid) *default_grid = persistent_grid();
+  if (default_grid) *default_grid = persistent_grid(plan->shape);
   return MONT_OK;
 }
 
@@ -2460,9 +2522,9 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   g.out = d_out;
   g.scr = scr;
   g.spin_limit = spin_limit ? spin_limit : (1u << 24);
-  uint32_t gsz = grid > 0 ? (uint32_t)grid : (uint32_t)persistent_grid();
+  uint32_t gsz = grid > 0 ? (uint32_t)grid : (uint32_t)persistent_grid(plan->shape);
   gsz = std::max(1u, std::min(gsz, plan->ntasks));
-  launch_persistent(g, gsz, s);
+  launch_persistent(g, gsz, s, plan->shape);
   if (plan->nfix > 0)
     // one workgroup per chunk: the chunks' record searches run in parallel
     hipLaunchKernelGGL(k_split_fix, dim3(plan->nchunks), dim3(256), 0, s, plan->ctx->d_primes,
@@ -2537,7 +2599,8 @@ extern "C" mont_status ntt_polymul_batch(const ntt_ctx* ctx, const polymul_desc*
   g.scr = scr;
   g.spin_limit = 1u << 24;
   g.dyn = 1;
-  launch_persistent(g, (uint32_t)persistent_grid(), s);
+  // the descriptors are on the device: the default shape (not a per-length one)
+  launch_persistent(g, (uint32_t)persistent_grid(g_ntt_tune), s, g_ntt_tune);
   // the chunk count is known only on the device: a grid that covers the
   // chunks of most batches at one workgroup each, striding beyond
   hipLaunchKernelGGL(k_split_fix, dim3(32768), dim3(256), 0, s, ctx->d_primes,

@@ -40,6 +40,8 @@ def register(L) -> None:
     L.ntt_ctx_read_twiddles.argtypes = [c_vp, c_int, c_vp, c_vp]
     L.ntt_tune_set.argtypes = [c_int, c_int, c_int]
     L.ntt_tune_get.argtypes = [ctypes.POINTER(c_int)] * 3
+    L.ntt_tune_set_length.argtypes = [c_int, c_int, c_int, c_int]
+    L.ntt_tune_get_length.argtypes = [c_int] + [ctypes.POINTER(c_int)] * 3
     L.ntt_forward.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp]
     L.ntt_inverse.argtypes = [c_vp, c_int, c_vp, c_u32, c_vp]
     L.ntt_polymul_scratch_bytes.argtypes = [c_u32, c_u32]
@@ -146,6 +148,18 @@ def tune_set(threads: int, radix_log: int, grid_mult: int = 1) -> None:
 def tune_get():
     t, r, g = c_int(), c_int(), c_int()
     mont.check(mont.lib().ntt_tune_get(ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)), "ntt_tune_get")
+    return t.value, r.value, g.value
+
+
+def tune_set_length(log2n: int, threads: int, radix_log: int = 4, grid_mult: int = 1) -> None:
+    """Launch shape for transforms of length 2^log2n (threads 0 removes the entry)."""
+    mont.check(mont.lib().ntt_tune_set_length(log2n, threads, radix_log, grid_mult), "ntt_tune_set_length")
+
+
+def tune_get_length(log2n: int):
+    t, r, g = c_int(), c_int(), c_int()
+    mont.check(mont.lib().ntt_tune_get_length(log2n, ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)),
+               "ntt_tune_get_length")
     return t.value, r.value, g.value
 
 

@@ -10,9 +10,15 @@ tests check every shape against the oracle).
 Tuned knobs:
   * elementwise (per op: to, from, mul, muladd, pow): threads per workgroup
     {64, 128, 256, 512} x 128-bit vectors per lane {1, 2, 4} x non-temporal {0, 1};
-  * transforms (one setting for all transform kernels): threads per
-    workgroup {256, 512, 1024} x largest register round {3, 4} stages, and
-    the persistent grid as a multiple of the resident workgroup count.
+  * transforms: threads per workgroup {256, 512, 1024} x largest register
+    round {3, 4} stages, and the persistent grid as a multiple of the
+    resident workgroup count: one default for all lengths (timed on the
+    2048-product batch) and one shape per length bucket (LEN_BUCKETS, timed
+    on a single product's plain launches and on a batch of products of that
+    length), which plain launches use by their length and plans by the
+    length that carries most of their butterflies.  The transform kernels
+    execute the same instructions for every prime below 2^31, so the buckets
+    are keyed by length only.
 
 Usage:  python -m paper_1609_00999_amd.tune [--out PATH] [--quick]
 """
@@ -32,6 +38,8 @@ DEFAULT_CACHE = os.path.join(PKG, "tune_cache.json")
 ELEM_SHAPES = [(b, v, nt) for b in (64, 128, 256, 512) for v in (1, 2, 4) for nt in (1, 0)]
 NTT_SHAPES = [(t, r) for t in (256, 512, 1024) for r in (3, 4)]
 GRID_MULTS = (1, 2)
+# (first, last) log2 lengths of each bucket; the bucket is timed at its last length
+LEN_BUCKETS = ((0, 13), (14, 16), (17, 19), (20, 21), (22, 23))
 applied: dict = {}
 
 
@@ -116,6 +124,18 @@ def apply(cache: dict, arch: str, lib) -> dict:
             applied[fam] = cfg
         else:
             rejected(fam, cfg, "status %d" % st)
+    for key, entry in sorted(cache.get(arch, {}).get("ntt_len", {}).items()):
+        try:
+            lo, hi = (int(x) for x in key.split("-"))
+            cfg = [int(x) for x in entry["config"]]
+            sts = [lib.ntt_tune_set_length(n, cfg[0], cfg[1], cfg[2]) for n in range(lo, hi + 1)]
+        except (TypeError, ValueError, IndexError, KeyError, AttributeError) as e:
+            rejected("ntt_len " + key, entry, e)
+            continue
+        if all(st == 0 for st in sts):
+            applied["ntt_len_" + key] = cfg
+        else:
+            rejected("ntt_len " + key, cfg, "status %r" % sts)
     cfg = choose(cache, arch, "ntt")
     if cfg:
         try:
@@ -189,25 +209,85 @@ def tune_ntt(batch=None, reps: int = 3):
     from . import workloads as wl
     batch = batch or wl.polymul_batch()
     ctx = ntt.Context(wl.PRIMES_NTT, 23)
-    plan = ntt.Plan.from_batch(ctx, batch)
     din = torch.from_numpy(batch.coeffs.view(np.int32)).cuda()
     dout = torch.empty(batch.out_len, dtype=torch.int32, device="cuda")
-    scr = plan.alloc_scratch()
     L = mont.lib()
     res = []
+    # per-length entries could override the default for the plan: time the
+    # default alone (a plan takes its launch shape when it is created); the
+    # per-length tuning runs afterwards
+    for n in range(24):
+        ntt.tune_set_length(n, 0)
+    scr = None
     for threads, radix in NTT_SHAPES:
         for gm in GRID_MULTS:
             mont.check(L.ntt_tune_set(threads, radix, gm), "ntt_tune_set")
+            plan = ntt.Plan.from_batch(ctx, batch)
+            if scr is None:
+                scr = plan.alloc_scratch()
             t = _time(torch, lambda: plan.execute(din, dout, scr), reps)
             res.append(((threads, radix, gm), t))
+            plan.close()
     # A larger grid multiplier only adds workgroups that find the queue empty;
     # within 1 % of the fastest batch the smaller grid wins, since it costs
     # less launch latency when a batch is small (a serving loop).
     best = best_entry(res, tie=0.01, cost=lambda c: c[2])
     mont.check(L.ntt_tune_set(*best["config"]), "ntt_tune_set")
-    plan.close()
     ctx.close()
     return best
+
+
+def tune_ntt_lengths(reps: int = 3, buckets=LEN_BUCKETS):
+    """One launch shape per length bucket: each shape is timed on one product
+    of the bucket's longest length (plain launches) and on a batch of
+    products of that length (one persistent launch); the shape with the
+    least sum of the two times, each relative to its fastest, wins."""
+    import torch
+    from . import ntt
+    from . import workloads as wl
+    ctx = ntt.Context(wl.PRIMES_NTT, 23)
+    rng = np.random.default_rng(11)
+    out = {}
+    try:
+        for lo, hi in buckets:
+            n = hi
+            d = (1 << (n - 1)) - 1                       # one product of length 2^n - 1
+            a = torch.randint(0, wl.PRIMES_NTT[0], (d + 1,), dtype=torch.int64, device="cuda").to(torch.int32)
+            pout = torch.empty(2 * d + 1, dtype=torch.int32, device="cuda")
+            pscr = torch.empty(max(1, ntt.scratch_bytes(d, d) // 4), dtype=torch.int32, device="cuda")
+            # products whose length lies in (0.9 N, N]: each is one whole
+            # product of length N = 2^n (no split, no truncated transform),
+            # so the plan takes this length's shape
+            count = max(8, min(512, 1 << max(0, 24 - n)))
+            degs = rng.integers(int(0.45 * (1 << n)), 1 << (n - 1), count)
+            batch = wl.pack_products(wl.PRIMES_NTT, rng.integers(0, 8, count), degs, degs, rng)
+            din = torch.from_numpy(batch.coeffs.view(np.int32)).cuda()
+            dout = torch.empty(batch.out_len, dtype=torch.int32, device="cuda")
+            plain, batched = {}, {}
+            for threads, radix in NTT_SHAPES:
+                for m in range(lo, hi + 1):
+                    ntt.tune_set_length(m, threads, radix, 1)
+                plain[(threads, radix)] = _time(torch, lambda: ntt.polymul(ctx, 0, a, a, out=pout, scratch=pscr), reps)
+                for gm in GRID_MULTS:
+                    for m in range(lo, hi + 1):
+                        ntt.tune_set_length(m, threads, radix, gm)
+                    plan = ntt.Plan.from_batch(ctx, batch)
+                    scr = plan.alloc_scratch()
+                    batched[(threads, radix, gm)] = _time(torch, lambda: plan.execute(din, dout, scr), reps)
+                    plan.close()
+                    del scr
+            p0, b0 = min(plain.values()), min(batched.values())
+            res = [(cfg, plain[cfg[:2]] / p0 + t / b0) for cfg, t in batched.items()]
+            best = best_entry(res, tie=0.01, cost=lambda c: c[2])
+            best["plain_seconds"] = {"%d_%d" % k: v for k, v in plain.items()}
+            best["batch_seconds"] = {"%d_%d_%d" % k: v for k, v in batched.items()}
+            cfg = best["config"]
+            for m in range(lo, hi + 1):
+                ntt.tune_set_length(m, cfg[0], cfg[1], cfg[2])
+            out["%d-%d" % (lo, hi)] = best
+    finally:
+        ctx.close()
+    return out
 
 
 def main():
@@ -225,6 +305,9 @@ def main():
     entry = tune_ntt()
     merge(cache, arch, "ntt", "batch2048", entry)
     print("ntt batch2048 -> %s (%.3f ms)" % (entry["config"], entry["seconds"] * 1e3), flush=True)
+    for key, e in tune_ntt_lengths().items():
+        merge(cache, arch, "ntt_len", key, e)
+        print("ntt lengths 2^%s -> %s (relative score %.3f)" % (key, e["config"], e["seconds"]), flush=True)
     print("saved %s in %.1f s" % (save(cache, args.out), time.time() - t0))
 
 

@@ -84,3 +84,40 @@ def test_transform_shapes(mods):
     finally:
         ntt.tune_set(*old)
         ctx.close()
+
+
+def test_per_length_shapes_keep_results(mods):
+    """Different launch shapes for different transform lengths (plain
+    launches by their length, a plan by its dominant length) leave every
+    product exact."""
+    mont, ntt, tune = mods
+    ctx = ntt.Context(wl.PRIMES_NTT, 23)
+    rng = np.random.default_rng(6)
+    batch = wl.pack_products(wl.PRIMES_NTT, rng.integers(0, 8, 30), wl.log_uniform(rng, 0, 19, 30),
+                             wl.log_uniform(rng, 0, 19, 30), rng)
+    ref = np.concatenate(oracle.polymul_many([batch.operands(i) for i in range(batch.count)]))
+    din = dev(batch.coeffs)
+    saved = [ntt.tune_get_length(n) for n in range(24)]
+    try:
+        shapes = [(256, 3, 1), (1024, 4, 2), (512, 3, 1), (256, 4, 2), (1024, 3, 1), (512, 4, 2)]
+        for rep in range(3):
+            for n in range(24):
+                ntt.tune_set_length(n, *shapes[(n + rep) % len(shapes)])
+            plan = ntt.Plan.from_batch(ctx, batch)
+            out = torch.zeros(batch.out_len, dtype=torch.int32, device="cuda")
+            scr = plan.alloc_scratch()
+            plan.execute(din, out, scr)
+            assert plan.status(scr) == 0
+            assert np.array_equal(host(out), ref), rep
+            plan.close()
+            for i in (0, batch.count // 2, batch.count - 1):
+                P, a, b = batch.operands(i)
+                got = host(ntt.polymul(ctx, wl.PRIMES_NTT.index(P), dev(a), dev(b)))
+                assert np.array_equal(got, oracle.polymul(P, a, b)), (rep, i)
+    finally:
+        for n in range(24):
+            ntt.tune_set_length(n, 0)
+        for n, sh in enumerate(saved):
+            if sh != ntt.tune_get():
+                ntt.tune_set_length(n, *sh)
+        ctx.close()

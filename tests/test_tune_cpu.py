@@ -16,6 +16,10 @@ class FakeLib:
         self.calls.append(("ntt", threads, radix, gm))
         return 0
 
+    def ntt_tune_set_length(self, n, threads, radix, gm):
+        self.calls.append(("ntt_len", n, threads, radix, gm))
+        return 0
+
 
 def test_best_entry_and_choose(tmp_path):
     res = [((256, 1, 1), 3.0), ((512, 2, 0), 1.0), ((256, 4, 1), 2.0)]
@@ -99,3 +103,38 @@ def test_cache_problems_are_reported(tmp_path):
     with warnings.catch_warnings():
         warnings.simplefilter("error")
         assert tune.load(os.path.join(str(tmp_path), "missing.json")) == {}   # no cache yet: silent
+
+
+def test_apply_sets_per_length_shapes():
+    """Per-length buckets set every length of their range through the C ABI."""
+    cache = {"gfx950": {"ntt_len": {"14-16": {"config": [256, 4, 1]}, "22-23": {"config": [1024, 3, 2]}}}}
+    lib = FakeLib()
+    applied = tune.apply(cache, "gfx950", lib)
+    assert applied == {"ntt_len_14-16": [256, 4, 1], "ntt_len_22-23": [1024, 3, 2]}
+    assert [c for c in lib.calls if c[0] == "ntt_len"] == [("ntt_len", n, 256, 4, 1) for n in (14, 15, 16)] + \
+        [("ntt_len", n, 1024, 3, 2) for n in (22, 23)]
+    import pytest
+    with pytest.warns(RuntimeWarning, match="ntt_len"):
+        assert tune.apply({"gfx950": {"ntt_len": {"x": {"config": [1]}}}}, "gfx950", FakeLib()) == {}
+    assert [b for b in tune.LEN_BUCKETS] == sorted(tune.LEN_BUCKETS)
+    covered = [n for lo, hi in tune.LEN_BUCKETS for n in range(lo, hi + 1)]
+    assert covered == list(range(24))
+
+
+def test_per_length_shapes_through_the_abi():
+    """ntt_tune_set_length / get_length (host only): an entry overrides the
+    default for its length only; threads 0 removes it; bad shapes are refused."""
+    import ctypes
+    from paper_1609_00999_amd import mont
+    L = mont.lib()
+    t, r, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    L.ntt_tune_set(512, 4, 1)
+    assert L.ntt_tune_set_length(16, 256, 3, 2) == 0
+    assert L.ntt_tune_get_length(16, ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)) == 0
+    assert (t.value, r.value, g.value) == (256, 3, 2)
+    assert L.ntt_tune_get_length(17, ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)) == 0
+    assert (t.value, r.value, g.value) == (512, 4, 1)
+    assert L.ntt_tune_set_length(16, 0, 0, 0) == 0
+    assert L.ntt_tune_get_length(16, ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)) == 0
+    assert (t.value, r.value, g.value) == (512, 4, 1)
+    assert L.ntt_tune_set_length(24, 512, 4, 1) == -1 and L.ntt_tune_set_length(5, 300, 4, 1) == -1
