@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--extras-only", default=None,
                     help="comma list out of %s: run only these side measurements, print them as one "
                          "JSON object and skip the headline step (for profiling runs)" % ",".join(EXTRAS))
+    ap.add_argument("--serving-frozen-only", action="store_true",
+                    help="the serving extra runs only the batched loop at the frozen rate (for kernel traces)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2^28-element int32 copy kernel (bitwise_not) three times, "
                          "whose HBM counters calibrate FETCH_SIZE / WRITE_SIZE")
@@ -84,7 +86,8 @@ def main():
         if bad:
             raise SystemExit("unknown extras: %s (choose from %s)" % (bad, ", ".join(EXTRAS)))
         leg = None if args.no_cpu_baseline else CpuBaselineLeg()
-        print(json.dumps({"extras": extras(torch, mont, wl, dev, which, leg=leg)}), flush=True)
+        print(json.dumps({"extras": extras(torch, mont, wl, dev, which, leg=leg,
+                                           serving_frozen_only=args.serving_frozen_only)}), flush=True)
         return
 
     # ---------------- inputs, resident in HBM ----------------
@@ -291,7 +294,7 @@ def timed(torch, fn, reps=5, warmup=1):
 EXTRAS = ("pipeline", "pow", "reductions", "vectors", "mont64", "crt", "polymul", "serving")
 
 
-def extras(torch, mont, wl, dev, which=EXTRAS, leg=None):
+def extras(torch, mont, wl, dev, which=EXTRAS, leg=None, serving_frozen_only=False):
     """Side measurements of the other rows, by name (EXTRAS).  With the CPU
     baseline leg, samples of the results are checked against the oracle and
     the power and batch rows also time the oracle on a bounded sample."""
@@ -317,7 +320,7 @@ def extras(torch, mont, wl, dev, which=EXTRAS, leg=None):
     if leg is not None and "polymul" in which:
         out["polymul_batch_2048"]["cpu_oracle"] = leg.polymul_sample(wl)
     if "serving" in which:
-        out["serving"] = serving_extra(torch, wl, dev, leg=leg)
+        out["serving"] = serving_extra(torch, wl, dev, leg=leg, frozen_only=serving_frozen_only)
     return out
 
 
@@ -532,7 +535,7 @@ def _at_rate(reqs, rate_from, rate_to, count):
 
 
 def serving_extra(torch, wl, dev, count=SERVE_REQUESTS + SERVE_WARMUP, rate=SERVE_RATE, warmup=SERVE_WARMUP,
-                  leg=None):
+                  leg=None, frozen_only=False):
     """Poisson stream of elementwise (n log-uniform 2^10..2^24) and polynomial
     (degree log-uniform 2^10..2^22) requests over the 8 primes: continuous
     batching on 4 slots against per-request plain launches.  Reported: the
@@ -585,6 +588,11 @@ def serving_extra(torch, wl, dev, count=SERVE_REQUESTS + SERVE_WARMUP, rate=SERV
         j.result = None
     del stats
     ex.keep = False
+    if frozen_only:
+        ex.close()
+        ctx.close()
+        log("serving: %s" % res)
+        return res
     # saturated capacity: every request of a prefix arriving at once
     sat = _at_rate(reqs, rate, 1e9, SERVE_SAT_REQUESTS)
     _, s_sat = run_batched(sat, 0)
