@@ -183,9 +183,20 @@ MONT_API mont_status ntt_plan_info(const ntt_plan* plan, size_t* scratch_bytes, 
 
 /* The work one execution of the plan performs: REDC operations (three
  * transforms of (N/2) log2 N butterflies, N pointwise products and db+1
- * operand scalings per product as planned, after splitting) and the number
- * of split products.  Either output pointer may be NULL. */
+ * operand scalings per product as planned, after splitting, less the
+ * butterflies whose twiddle is 1, which run without a product: N (1 - 2^-r)
+ * per transform, r the size of the register round that holds stage 0, so
+ * the count depends on the plan's radix, ntt_plan_shape) and the number of
+ * split products.  Either output pointer may be NULL. */
 MONT_API mont_status ntt_plan_work(const ntt_plan* plan, uint64_t* redc, uint32_t* split_products);
+
+/* The launch shape the plan's persistent launch takes: threads per
+ * workgroup, log2 of the register-round radix, grid multiplier.  Chosen when
+ * the plan is created or updated: the shape tuned for a transform length
+ * when at least 90 % of the plan's butterflies are at that length, else the
+ * default shape (ntt_tune_set, ntt_tune_set_length).  Any output pointer may
+ * be NULL.  Errors: MONT_EINVAL (plan NULL). */
+MONT_API mont_status ntt_plan_shape(const ntt_plan* plan, int* threads, int* radix_log, int* grid_mult);
 
 /*
  * ntt_plan_execute -- zeroes the scratch header with a fill kernel, then runs

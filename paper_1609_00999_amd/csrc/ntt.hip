@@ -275,6 +275,25 @@ __host__ __device__ inline uint64_t slot_redc(const SlotShape& sh) {
   return r;
 }
 
+// Butterflies of a slot's three transforms whose twiddle is 1, which the
+// kernels run without a product (transforms of 2^rm-point register rounds):
+// those of stages t < r in the round holding stages 0 .. r-1, 2^n / 2^(t+1)
+// per stage and transform.  A multi-pass slot has that round in its row
+// pass (the last forward round of both operands and the first inverse round,
+// of the 13-stage row: r = 13 / ceil(13 / rm)); a one-task slot in its last
+// forward round (r = n / ceil(n / rm), both operands) and its first inverse
+// round (one more when rm does not divide the rounds evenly).
+__host__ __device__ inline uint64_t unit_bfly(int n, int rm) {
+  if (n <= 0) return 0;
+  const uint64_t N = 1ull << n;
+  const int lr = n > kRowLog ? kRowLog : n;
+  const int nr = (lr + rm - 1) / rm;
+  const int r_small = lr / nr, r_large = r_small + (lr % nr ? 1 : 0);
+  const uint64_t fwd = N - (N >> r_small);
+  if (n > kRowLog) return 3 * fwd;
+  return 2 * fwd + (N - (N >> r_large));
+}
+
 // REDC operations of a product's fix-up, counted on its second slot: a
 // block's untwist, the fold of the cyclic part and the halving, per fixed
 // coefficient.
@@ -344,6 +363,30 @@ __device__ __forceinline__ uint32_t ldg(const uint32_t* p, uint32_t i) {
   return ((gptr_u32)p)[i];
 }
 
+// Raw buffer loads (CDNA buffer instructions): a 128-bit resource in scalar
+// registers holds a base address and a size in bytes; each lane supplies a
+// 32-bit byte offset, and a constant part of the offset may ride in a scalar
+// register.  A load at or past the size returns 0 (the range check of raw,
+// unstrided buffers on the lane's offset), which gives a first round's zero
+// padding beyond the operand without a compare, and each address costs one
+// 32-bit add instead of a 64-bit address pair.  The base must be uniform
+// across the workgroup; it is read from the first lane.
+constexpr int kBufWord3 = 0x00020000;   // resource word 3 on gfx9: 32-bit data format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const uint32_t* p, uint32_t bytes) {
+  const uint64_t a = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)(((uint64_t)hi << 32) | lo), 0, (int)bytes, kBufWord3);
+}
+// Size of a first round's source: words 0 .. dvalid (all of the 32-bit range
+// when dvalid is the "no bound" value).
+__device__ __forceinline__ uint32_t src_bytes(uint32_t dvalid) {
+  return dvalid >= 0x3FFFFFFFu ? 0xFFFFFFFFu : (dvalid + 1) << 2;
+}
+__device__ __forceinline__ uint32_t buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff = 0) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0);
+}
+
 // The lane's index in the workgroup as the task bodies use it.  The empty asm
 // makes each read opaque, so what a task derives from it (group bases, LDS
 // addresses) is computed inside the persistent task loop rather than hoisted
@@ -378,7 +421,14 @@ __device__ __forceinline__ uint32_t bfly_lo(uint32_t x, uint32_t y, uint32_t w, 
 // The R radix-2 stages of one register round on a group of 2^R residues.
 // Stage t pairs elements 2^t apart; its twiddle for pair (j, j + 2^t) is
 // w[2^t - 1 + (j mod 2^t)] (wn holds P - w for the forward butterfly).
-template <int R>
+//
+// UNIT: the group is one whose twiddles for j mod 2^t = 0 are w^0 = 1 (the
+// round holding stages 0 .. R-1 of a block that starts at twiddle offset 0:
+// rows, and whole transforms in one workgroup).  Those butterflies add and
+// subtract without a product: REDC(y R) = y exactly, so the results are the
+// same residues.  They are half of stage 0, a quarter of stage 1, and so on:
+// N (1 - 2^-R) of a transform's (N/2) log2 N butterflies.
+template <int R, bool UNIT = false>
 __device__ __forceinline__ void dif_stages(uint32_t* v, const uint32_t* w, const uint32_t* wn, Mod md) {
   constexpr int E = 1 << R;
 #pragma unroll
@@ -389,12 +439,13 @@ __device__ __forceinline__ void dif_stages(uint32_t* v, const uint32_t* w, const
       if (j & d) continue;
       const uint32_t x = v[j], y = v[j + d];
       v[j] = madd(x, y, md.P);
-      v[j + d] = bfly_lo(x, y, w[d - 1 + (j & (d - 1))], wn[d - 1 + (j & (d - 1))], md);
+      if (UNIT && (j & (d - 1)) == 0) v[j + d] = msub(x, y, md.P);
+      else v[j + d] = bfly_lo(x, y, w[d - 1 + (j & (d - 1))], wn[d - 1 + (j & (d - 1))], md);
     }
   }
 }
 
-template <int R>
+template <int R, bool UNIT = false>
 __device__ __forceinline__ void dit_stages(uint32_t* v, const uint32_t* w, Mod md) {
   constexpr int E = 1 << R;
 #pragma unroll
@@ -404,16 +455,16 @@ __device__ __forceinline__ void dit_stages(uint32_t* v, const uint32_t* w, Mod m
     for (int j = 0; j < E; j++) {
       if (j & d) continue;
       const uint32_t x = v[j];
-      const uint32_t y = mmul(v[j + d], w[d - 1 + (j & (d - 1))], md);
+      const uint32_t y = UNIT && (j & (d - 1)) == 0 ? v[j + d] : mmul(v[j + d], w[d - 1 + (j & (d - 1))], md);
       v[j] = madd(x, y, md.P);
       v[j + d] = msub(x, y, md.P);
     }
   }
 }
 
-template <int NT, int NA, int R, bool INV>
-__device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int s_lo, int lc, int rs,
-                                          uint32_t colbase, const uint32_t* tw, Mod md) {
+template <int NT, int NA, int R, bool INV, bool UNIT>
+__device__ __forceinline__ void lds_round_body(uint32_t* X, int off, uint32_t M, int s_lo, int lc, int rs,
+                                               uint32_t colbase, const uint32_t* tw, Mod md) {
   constexpr int E = 1 << R;
   const int a_lo = s_lo + lc;                      // LDS address bit of stage s_lo
   const uint32_t lomask = (1u << a_lo) - 1;
@@ -440,13 +491,23 @@ __device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int 
       uint32_t v[E];
 #pragma unroll
       for (int j = 0; j < E; j++) v[j] = X[pb ^ lds_at((uint32_t)j << a_lo)];
-      if constexpr (!INV) dif_stages<R>(v, w, wn, md);
-      else dit_stages<R>(v, w, md);
+      if constexpr (!INV) dif_stages<R, UNIT>(v, w, wn, md);
+      else dit_stages<R, UNIT>(v, w, md);
 #pragma unroll
       for (int j = 0; j < E; j++) X[pb ^ lds_at((uint32_t)j << a_lo)] = v[j];
     }
   }
   __syncthreads();
+}
+
+// A round over stages s_lo .. s_lo + R - 1.  The round holding stage 0 of
+// blocks whose twiddles start at offset 0 (one column, offset 0) skips the
+// products by twiddle 1.
+template <int NT, int NA, int R, bool INV>
+__device__ __forceinline__ void lds_round(uint32_t* X, int off, uint32_t M, int s_lo, int lc, int rs,
+                                          uint32_t colbase, const uint32_t* tw, Mod md) {
+  if (s_lo == 0 && lc == 0 && colbase == 0) lds_round_body<NT, NA, R, INV, true>(X, off, M, 0, 0, rs, 0u, tw, md);
+  else lds_round_body<NT, NA, R, INV, false>(X, off, M, s_lo, lc, rs, colbase, tw, md);
 }
 
 template <int NT, int NA, bool INV, int RM>
@@ -584,21 +645,88 @@ template <int NT, int NA, int R, bool INV, int LR, int LC, int RS, int S_LO, boo
 __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t colbase, const uint32_t* tw,
                                                 Mod md, ColIO io = ColIO{}) {
   static_assert(NA == 1 || !(GIN || GOUT), "global rounds take one operand");
+  static_assert(LC > 0 || RS == 0, "LC = 0 is the row pass (unit twiddles in its stage-0 round)");
   constexpr int E = 1 << R;
   constexpr int A_LO = S_LO + LC;
   constexpr uint32_t lomask = (1u << A_LO) - 1;
   constexpr uint32_t ngroups = (1u << (LR + LC)) >> R;
+  constexpr int GS = S_LO + RS;
+  if constexpr (GIN && ngroups == 2 * NT) {
+    // A round that loads from HBM with two groups per lane (the first round
+    // of a column tile): the lane issues both groups' data loads before any
+    // arithmetic, so it waits on HBM once per round instead of once per
+    // group.  (The group loop below cannot overlap them: its start, the lane
+    // index, is opaque to the compiler.)  The second group's twiddles are
+    // loaded after the first group's arithmetic (they come from the
+    // cache-resident tables), which keeps the round within the register
+    // budget.  Truncated-transform blocks take the loop.
+    if (!io.twist) {
+      const uint32_t tid = task_tid();
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(io.src, src_bytes(io.dvalid));
+      const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tw, 0xFFFFFFFFu);
+      uint32_t v[2][E], gi0[2], base[2], c[2];
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        const uint32_t g = tid + (uint32_t)q * NT;
+        base[q] = ((g & ~lomask) << R) | (g & lomask);
+        c[q] = base[q] & ((1u << LC) - 1);
+        gi0[q] = colbase + c[q] + ((base[q] >> LC) << RS);
+#pragma unroll
+        for (int j = 0; j < E; j++) v[q][j] = buf_ld(rs, (gi0[q] + ((uint32_t)j << GS)) << 2);
+      }
+#pragma unroll
+      for (int q = 0; q < 2; q++) {
+        // keeps the scheduler from hoisting the second group's twiddle loads
+        // above the first group's arithmetic
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t t0 = (colbase + c[q] + (((base[q] >> LC) & ((1u << S_LO) - 1)) << RS)) << 2;
+        uint32_t w[E - 1];
+#pragma unroll
+        for (int t = 0; t < R; t++)
+#pragma unroll
+          for (int jj = 0; jj < (1 << t); jj++)
+            w[(1 << t) - 1 + jj] = buf_ld(rt, t0, ((1u << (S_LO + t + RS)) + ((uint32_t)jj << (S_LO + RS))) << 2);
+        if (io.scale) {
+#pragma unroll
+          for (int j = 0; j < E; j++) v[q][j] = mmul(v[q][j], io.scale, md);
+        }
+        if constexpr (!INV) {
+          uint32_t wn[E - 1];
+#pragma unroll
+          for (int k = 0; k < E - 1; k++) wn[k] = md.P - w[k];
+          dif_stages<R>(v[q], w, wn, md);
+        } else {
+          dit_stages<R>(v[q], w, md);
+        }
+        if constexpr (GOUT) {
+#pragma unroll
+          for (int j = 0; j < E; j++) {
+            const uint32_t gi = gi0[q] + ((uint32_t)j << GS);
+            if (gi < io.nout) st_out<COH>(io.dst + gi, v[q][j]);
+          }
+        } else {
+          uint32_t ad[E];
+          fill_group_addr<A_LO, R, 0>(ad, base[q], lds_at(base[q]));
+#pragma unroll
+          for (int j = 0; j < E; j++) X[ad[j]] = v[q][j];
+        }
+      }
+      __syncthreads();
+      return;
+    }
+  }
+  const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tw, 0xFFFFFFFFu);
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(GIN ? io.src : tw, GIN ? src_bytes(io.dvalid) : 0u);
   for (uint32_t g = task_tid(); g < ngroups; g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
     const uint32_t c = base & ((1u << LC) - 1);
-    const uint32_t t0 = colbase + c + (((base >> LC) & ((1u << S_LO) - 1)) << RS);
-    const uint32_t* twg = tw + t0;
+    const uint32_t t0 = (colbase + c + (((base >> LC) & ((1u << S_LO) - 1)) << RS)) << 2;
     uint32_t w[E - 1];
 #pragma unroll
     for (int t = 0; t < R; t++)
 #pragma unroll
       for (int jj = 0; jj < (1 << t); jj++)
-        w[(1 << t) - 1 + jj] = ldg(twg, (1u << (S_LO + t + RS)) + ((uint32_t)jj << (S_LO + RS)));
+        w[(1 << t) - 1 + jj] = buf_ld(rt, t0, ((1u << (S_LO + t + RS)) + ((uint32_t)jj << (S_LO + RS))) << 2);
     uint32_t wn[E - 1];
     if constexpr (!INV) {
 #pragma unroll
@@ -613,7 +741,6 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
       fill_group_addr<A_LO, R, 0>(ad, yb, pb);
       // global index of the group's element j
       const uint32_t gi0 = colbase + c + ((base >> LC) << RS);
-      constexpr int GS = S_LO + RS;
       if constexpr (GIN) {
         if (io.twist) {
           // fold modulo x^s - w^s (operands are shorter than 4s), then twist
@@ -630,10 +757,7 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
           }
         } else {
 #pragma unroll
-          for (int j = 0; j < E; j++) {
-            const uint32_t gi = gi0 + ((uint32_t)j << GS);
-            v[j] = gi <= io.dvalid ? io.src[gi] : 0u;
-          }
+          for (int j = 0; j < E; j++) v[j] = buf_ld(rs, (gi0 + ((uint32_t)j << GS)) << 2);
         }
         if (io.scale) {
 #pragma unroll
@@ -643,8 +767,10 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
 #pragma unroll
         for (int j = 0; j < E; j++) v[j] = X[ad[j]];
       }
-      if constexpr (!INV) dif_stages<R>(v, w, wn, md);
-      else dit_stages<R>(v, w, md);
+      // LC = 0 is the row pass, whose blocks start at twiddle offset 0
+      // (colbase = 0): its round holding stage 0 skips the unit twiddles
+      if constexpr (!INV) dif_stages<R, S_LO == 0 && LC == 0>(v, w, wn, md);
+      else dit_stages<R, S_LO == 0 && LC == 0>(v, w, md);
       if constexpr (GOUT) {
 #pragma unroll
         for (int j = 0; j < E; j++) {
@@ -698,22 +824,25 @@ __device__ __forceinline__ void row_round_in(uint32_t* X, uint32_t L, const uint
   static_assert(S_LO >= 9, "the group stride must be above the swizzled bits");
   constexpr int E = 1 << R;
   constexpr uint32_t lomask = (1u << S_LO) - 1;
+  const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tw, 0xFFFFFFFFu);
+  const __amdgpu_buffer_rsrc_t ra = buf_rsrc(gA, 0xFFFFFFFFu);
+  const __amdgpu_buffer_rsrc_t rb = buf_rsrc(gB, 0xFFFFFFFFu);
   for (uint32_t g = task_tid(); g < ((1u << kRowLog) >> R); g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
-    const uint32_t* twg = tw + (base & lomask);
+    const uint32_t t0 = (base & lomask) << 2;
     uint32_t w[E - 1], wn[E - 1];
 #pragma unroll
     for (int t = 0; t < R; t++)
 #pragma unroll
-      for (int jj = 0; jj < (1 << t); jj++) w[(1 << t) - 1 + jj] = ldg(twg, (1u << (S_LO + t)) + ((uint32_t)jj << S_LO));
+      for (int jj = 0; jj < (1 << t); jj++)
+        w[(1 << t) - 1 + jj] = buf_ld(rt, t0, ((1u << (S_LO + t)) + ((uint32_t)jj << S_LO)) << 2);
 #pragma unroll
     for (int k = 0; k < E - 1; k++) wn[k] = md.P - w[k];
 #pragma unroll
     for (int a = 0; a < 2; a++) {
-      const uint32_t* src = (a == 0 ? gA : gB) + base;
       uint32_t v[E];
 #pragma unroll
-      for (int j = 0; j < E; j++) v[j] = src[(uint32_t)j << S_LO];
+      for (int j = 0; j < E; j++) v[j] = buf_ld(a == 0 ? ra : rb, base << 2, ((uint32_t)j << S_LO) << 2);
       dif_stages<R>(v, w, wn, md);
       const uint32_t pb = lds_at((uint32_t)a * L + base);
 #pragma unroll
@@ -728,14 +857,16 @@ __device__ __forceinline__ void row_round_out(const uint32_t* X, uint32_t* gA, c
   static_assert(S_LO >= 9, "the group stride must be above the swizzled bits");
   constexpr int E = 1 << R;
   constexpr uint32_t lomask = (1u << S_LO) - 1;
+  const __amdgpu_buffer_rsrc_t rt = buf_rsrc(tw, 0xFFFFFFFFu);
   for (uint32_t g = task_tid(); g < ((1u << kRowLog) >> R); g += NT) {
     const uint32_t base = ((g & ~lomask) << R) | (g & lomask);
-    const uint32_t* twg = tw + (base & lomask);
+    const uint32_t t0 = (base & lomask) << 2;
     uint32_t w[E - 1];
 #pragma unroll
     for (int t = 0; t < R; t++)
 #pragma unroll
-      for (int jj = 0; jj < (1 << t); jj++) w[(1 << t) - 1 + jj] = ldg(twg, (1u << (S_LO + t)) + ((uint32_t)jj << S_LO));
+      for (int jj = 0; jj < (1 << t); jj++)
+        w[(1 << t) - 1 + jj] = buf_ld(rt, t0, ((1u << (S_LO + t)) + ((uint32_t)jj << S_LO)) << 2);
     const uint32_t pb = lds_at(base);
     uint32_t v[E];
 #pragma unroll
@@ -776,11 +907,11 @@ __device__ __forceinline__ void row_round_fused(uint32_t* X, uint32_t L, const u
       va[j] = X[pa ^ (uint32_t)j];
       vb[j] = X[pb ^ (uint32_t)j];
     }
-    dif_stages<R>(va, wf, wfn, md);
-    dif_stages<R>(vb, wf, wfn, md);
+    dif_stages<R, true>(va, wf, wfn, md);
+    dif_stages<R, true>(vb, wf, wfn, md);
 #pragma unroll
     for (int j = 0; j < E; j++) va[j] = mmul(va[j], vb[j], md);
-    dit_stages<R>(va, wi, md);
+    dit_stages<R, true>(va, wi, md);
 #pragma unroll
     for (int j = 0; j < E; j++) X[pa ^ (uint32_t)j] = va[j];
   }
@@ -1749,6 +1880,13 @@ NttTune plan_shape(const std::vector<ProdDev>& prods) {
   return total > 0 && work[best] >= 0.9 * total ? shape_for(best) : g_ntt_tune;
 }
 
+// Butterflies with a unit twiddle that a plan's products skip at radix 2^rm.
+uint64_t plan_unit_bfly(const std::vector<ProdDev>& prods, int rm) {
+  uint64_t u = 0;
+  for (const ProdDev& pd : prods) u += unit_bfly((int)pd.n, rm);
+  return u;
+}
+
 template <int NT, int RM>
 void launch_direct_v(const DirectArgs& g, uint32_t grid, hipStream_t s) {
   hipLaunchKernelGGL((k_ntt_direct<NT, RM>), dim3(grid), dim3(NT), 0, s, g);
@@ -2339,7 +2477,6 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
   plan->ntasks = (uint32_t)tasks.size();
   plan->nfix = (uint32_t)fixes.size();
   plan->nchunks = nchunks;
-  plan->redc = redc;
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
@@ -2360,6 +2497,7 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
     }
   }
   plan->shape = plan_shape(prods);
+  plan->redc = redc - plan_unit_bfly(prods, plan->shape.radix_log);
   plan->default_grid = persistent_grid(plan->shape);
   *out = plan;
   return MONT_OK;
@@ -2443,11 +2581,11 @@ extern "C" mont_status ntt_plan_update(ntt_plan* plan, const polymul_desc* descs
   plan->ntasks = (uint32_t)tasks.size();
   plan->nfix = (uint32_t)fixes.size();
   plan->nchunks = nchunks;
-  plan->redc = redc;
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
   plan->shape = plan_shape(prods);
+  plan->redc = redc - plan_unit_bfly(prods, plan->shape.radix_log);
   plan->default_grid = persistent_grid(plan->shape);
   plan->upd_us[3] = us_since(t0);
   return MONT_OK;
@@ -2489,6 +2627,14 @@ extern "C" mont_status ntt_plan_work(const ntt_plan* plan, uint64_t* redc, uint3
   if (!plan) return MONT_EINVAL;
   if (redc) *redc = plan->redc;
   if (split_products) *split_products = plan->nfix;
+  return MONT_OK;
+}
+
+extern "C" mont_status ntt_plan_shape(const ntt_plan* plan, int* threads, int* radix_log, int* grid_mult) {
+  if (!plan) return MONT_EINVAL;
+  if (threads) *threads = plan->shape.threads;
+  if (radix_log) *radix_log = plan->shape.radix_log;
+  if (grid_mult) *grid_mult = plan->shape.grid_mult;
   return MONT_OK;
 }
 

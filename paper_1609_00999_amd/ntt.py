@@ -50,6 +50,7 @@ def register(L) -> None:
     L.ntt_plan_create.argtypes = [c_vp, c_vp, c_int, c_u32, vpp]
     L.ntt_plan_reserve.argtypes = [c_vp, c_int, c_u32, vpp]
     L.ntt_plan_work.argtypes = [c_vp, ctypes.POINTER(c_u64), ctypes.POINTER(c_u32)]
+    L.ntt_plan_shape.argtypes = [c_vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
     L.ntt_plan_task_count.argtypes = [c_u32, c_u32]
     L.ntt_plan_task_count.restype = c_u32
     L.ntt_plan_update.argtypes = [c_vp, c_vp, c_int, c_u32, c_vp]
@@ -268,6 +269,13 @@ class Plan:
         r, sp = c_u64(), c_u32()
         mont.check(mont.lib().ntt_plan_work(self.handle, ctypes.byref(r), ctypes.byref(sp)), "ntt_plan_work")
         return r.value, sp.value
+
+    def shape(self):
+        """(threads, log2 radix, grid multiplier) of the plan's persistent launch."""
+        t, r, g = c_int(), c_int(), c_int()
+        mont.check(mont.lib().ntt_plan_shape(self.handle, ctypes.byref(t), ctypes.byref(r), ctypes.byref(g)),
+                   "ntt_plan_shape")
+        return t.value, r.value, g.value
 
     def _info(self):
         sb, nt, iw, ow, g = c_size(), c_u32(), c_u64(), c_u64(), c_int()

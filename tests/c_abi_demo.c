@@ -225,6 +225,12 @@ static int device_checks(void) {
     check(ok, round == 0 ? "ntt_plan_execute, 2 products (lists in the launch)"
                          : "ntt_plan_execute, 6 products (lists uploaded)");
   }
+  {
+    int th = 0, rl = 0, gm = 0;
+    ok = ntt_plan_shape(pl, &th, &rl, &gm) == MONT_OK && (th == 256 || th == 512 || th == 1024) &&
+         (rl == 3 || rl == 4) && gm >= 1;
+    check(ok, "ntt_plan_shape");
+  }
   check(ntt_plan_destroy(pl) == MONT_OK, "ntt_plan_destroy");
 
   /* a one-call batch: six products whose descriptors sit in device memory

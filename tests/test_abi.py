@@ -166,5 +166,7 @@ def test_validation_of_the_next_rows_without_gpu(L):
     # plan queries
     L.ntt_plan_work.argtypes = [c_vp, c_vp, c_vp]
     assert L.ntt_plan_work(None, None, None) == EINVAL
+    L.ntt_plan_shape.argtypes = [c_vp, c_vp, c_vp, c_vp]
+    assert L.ntt_plan_shape(None, None, None, None) == EINVAL
     L.ntt_plan_task_count.restype = ctypes.c_uint32
     assert L.ntt_plan_task_count(0xFFFFFFFF, 0xFFFFFFFF) == 0                 # too long

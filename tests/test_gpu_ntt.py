@@ -5,6 +5,7 @@ import pytest
 
 import oracle
 from paper_1609_00999_amd import workloads as wl
+from test_unit_twiddles import unit_twiddle_butterflies
 
 pytestmark = pytest.mark.gpu
 
@@ -514,17 +515,18 @@ def test_split_special_values(N, ctx):
         assert all(int(got[i]) == c2[int(i)] for i in idx)
 
 
-def planned_work(da, db):
+def planned_work(da, db, rm=4):
     """The planning rules restated: (executed REDC, 1 if computed in two
     parts).  Two-block truncated transform when N >= 2^18, both operands
     below h = N/2 and N/16 < m = L - h <= N/4 (block of N/8 points for m <=
     N/8, N/4 above); otherwise the split when the product is multi-pass, both
     operands are below h and the top product's length 2^nt >= 2m - 1 is at
-    most N/4; otherwise whole.  A product costs three transforms, N pointwise
-    products and db+1 scalings; a block scales all its N points and adds its
-    fold and twist products, and its fix-up m (h/s + 1)."""
+    most N/4; otherwise whole.  A product costs three transforms, less their
+    butterflies by a unit twiddle at radix 2^rm, N pointwise products and db+1
+    scalings; a block scales all its N points and adds its fold and twist
+    products, and its fix-up m (h/s + 1)."""
     def cost(n, dbb):
-        return 3 * (1 << n) // 2 * n + (1 << n) + dbb + 1
+        return 3 * (1 << n) // 2 * n - unit_twiddle_butterflies(n, rm) + (1 << n) + dbb + 1
 
     L = da + db + 1
     n = (L - 1).bit_length()
@@ -540,22 +542,36 @@ def planned_work(da, db):
     return cost(n, db), 0
 
 
-def test_plan_work_counts(N, ctx):
-    """ntt_plan_work reports the REDC of the products as planned (rules above)."""
+@pytest.mark.parametrize("radix_log", [3, 4])
+def test_plan_work_counts(N, ctx, radix_log):
+    """ntt_plan_work reports the REDC of the products as planned (rules
+    above), at the radix of the plan's shape."""
     rng = np.random.default_rng(5)
     shapes = SPLIT_SHAPES + TFT_SHAPES
     da = [s[0] for s in shapes]
     db = [s[1] for s in shapes]
     batch = wl.pack_products(PRIMES, rng.integers(0, len(PRIMES), len(da)), da, db, rng)
-    want, nsplit = 0, 0
-    for a, b in zip(da, db):
-        w, sp = planned_work(a, b)
-        want += w
-        nsplit += sp
-    plan = N.Plan.from_batch(ctx, batch)
-    assert plan.work() == (want, nsplit)
-    assert nsplit > 0
-    plan.close()
+    old = N.tune_get()
+    saved = [N.tune_get_length(n) for n in range(24)]
+    try:
+        N.tune_set(512, radix_log, 1)
+        for n in range(24):
+            N.tune_set_length(n, 0)
+        plan = N.Plan.from_batch(ctx, batch)
+        assert plan.shape() == (512, radix_log, 1)
+        want, nsplit = 0, 0
+        for a, b in zip(da, db):
+            w, sp = planned_work(a, b, radix_log)
+            want += w
+            nsplit += sp
+        assert plan.work() == (want, nsplit)
+        assert nsplit > 0
+        plan.close()
+    finally:
+        N.tune_set(*old)
+        for n, sh in enumerate(saved):
+            if sh[0]:
+                N.tune_set_length(n, *sh)
 
 
 def test_truncated_transform_shapes_vs_oracle(N, ctx):
