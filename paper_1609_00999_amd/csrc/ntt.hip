@@ -485,7 +485,7 @@ __device__ __forceinline__ void lds_round_body(uint32_t* X, int off, uint32_t M,
 #pragma unroll
       for (int k = 0; k < E - 1; k++) wn[k] = md.P - w[k];
     }
-#pragma nounroll
+#pragma unroll
     for (int a = 0; a < NA; a++) {
       const uint32_t pb = lds_at((uint32_t)(a * off) + base);
       uint32_t v[E];
@@ -732,7 +732,7 @@ __device__ __forceinline__ void lds_round_fixed(uint32_t* X, int off, uint32_t c
 #pragma unroll
       for (int k = 0; k < E - 1; k++) wn[k] = md.P - w[k];
     }
-#pragma nounroll
+#pragma unroll
     for (int a = 0; a < NA; a++) {
       const uint32_t yb = (uint32_t)(a * off) + base;
       const uint32_t pb = lds_at(yb);
