@@ -2339,7 +2339,11 @@ mont_status build_plan(const ntt_ctx* ctx, const polymul_desc* descs, int count,
   std::vector<int> big;
   for (int p = 0; p < np; p++)
     if (prods[p].n > (uint32_t)kRowLog) big.push_back(p);
-  std::stable_sort(big.begin(), big.end(), [&](int x, int y) { return prods[x].n > prods[y].n; });
+  // longest first; products of one length by prime, so that tasks that run
+  // together share one prime's twiddle tables in the caches
+  std::stable_sort(big.begin(), big.end(), [&](int x, int y) {
+    return prods[x].n != prods[y].n ? prods[x].n > prods[y].n : prods[x].prime_id < prods[y].prime_id;
+  });
   std::stable_sort(small.begin(), small.end(), [&](uint2 x, uint2 y) { return prods[x.x].n > prods[y.x].n; });
   tasks.reserve(product_task_total(prods));
   if (big.size() < kPipeMinProducts) {
