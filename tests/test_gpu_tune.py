@@ -121,3 +121,49 @@ def test_per_length_shapes_keep_results(mods):
             if sh != ntt.tune_get():
                 ntt.tune_set_length(n, *sh)
         ctx.close()
+
+
+def test_plan_shape_follows_dominant_length(mods):
+    """A plan with at least 90 % of its butterflies at one transform length
+    takes that length's launch shape, any other plan the default shape
+    (ntt_plan_shape), for created and for reserved plans alike; both give
+    the oracle's products."""
+    _, ntt, _ = mods
+    ctx = ntt.Context(wl.PRIMES_NTT, 23)
+    rng = np.random.default_rng(12)
+    old = ntt.tune_get()
+    saved = [ntt.tune_get_length(n) for n in range(24)]
+    reserved = ntt.Plan.reserve(ctx, 16, 1 << 14)
+    try:
+        for n in range(24):
+            ntt.tune_set_length(n, 0)
+        ntt.tune_set(512, 4, 1)
+        ntt.tune_set_length(16, 1024, 3, 2)
+        # degrees 30000 .. 32000: products of length 2^16, none split
+        one = wl.pack_products(wl.PRIMES_NTT, rng.integers(0, 8, 6), rng.integers(30000, 32000, 6),
+                               rng.integers(30000, 32000, 6), rng)
+        # lengths 2^11 .. 2^17, none with 90 % of the work
+        mixed = wl.pack_products(wl.PRIMES_NTT, rng.integers(0, 8, 4), [1000, 8000, 30000, 60000],
+                                 [1000, 8000, 30000, 60000], rng)
+        for batch, want in ((one, (1024, 3, 2)), (mixed, (512, 4, 1))):
+            ref = np.concatenate(oracle.polymul_many([batch.operands(i) for i in range(batch.count)]))
+            desc = ntt.make_descs(batch.prime_id, batch.da, batch.db, batch.a_off, batch.b_off, batch.c_off)
+            reserved.update(desc)
+            for plan in (ntt.Plan.from_batch(ctx, batch), reserved):
+                assert plan.shape() == want
+                out = torch.zeros(batch.out_len, dtype=torch.int32, device="cuda")
+                scr = plan.alloc_scratch()
+                plan.execute(dev(batch.coeffs), out, scr)
+                assert plan.status(scr) == 0
+                assert np.array_equal(host(out), ref), want
+                if plan is not reserved:
+                    plan.close()
+    finally:
+        reserved.close()
+        ntt.tune_set(*old)
+        for n in range(24):
+            ntt.tune_set_length(n, 0)
+        for n, sh in enumerate(saved):
+            if sh != ntt.tune_get():
+                ntt.tune_set_length(n, *sh)
+        ctx.close()
