@@ -1483,6 +1483,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   __shared__ uint32_t s_rowb[kPlanBuckets], s_colib[kPlanBuckets];   // same, row blocks and inverse tiles
   __shared__ uint32_t s_run[kPlanBuckets];          // slots of the length placed so far
   __shared__ uint32_t s_wc[kPlanWaves][kPlanBuckets];
+  // the multi-pass slots of the current chunk of slots: slot, first forward
+  // tile, first inverse tile and first row block task, tiles, blocks (their
+  // tasks are written by the whole workgroup)
+  __shared__ uint32_t s_eslot[kPlanThreads], s_ef0[kPlanThreads], s_ei0[kPlanThreads], s_er0[kPlanThreads];
+  __shared__ uint32_t s_ent[kPlanThreads], s_enb[kPlanThreads];
   __shared__ uint64_t s_wsum[kPlanWaves];
   __shared__ uint32_t s_C, s_R, s_half;
   __shared__ uint64_t s_data, s_chk;
@@ -1582,9 +1587,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
       if (lane == 0) s_wc[wave][k] = (uint32_t)__popcll(mask);
       if (b == k) inwave = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
     }
-    uint64_t wtot = 0, ctot = 0;
+    uint64_t wtot = 0, ctot = 0, etot = 0;
     const uint64_t woff = plan_scan(slot_words(sh, part), s_wsum, &wtot);    // barriers also publish s_wc
     const uint64_t coff = plan_scan(slot < nslots && part == 1 ? slot_chunks(sh, part) : 0u, s_wsum, &ctot);
+    const uint32_t ei = (uint32_t)plan_scan(sh.used && sh.n > kRowLog ? 1u : 0u, s_wsum, &etot);
     if (slot < nslots) {
       uint32_t rank = 0;
       if (sh.used) {
@@ -1618,15 +1624,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
           const uint32_t at = q < half ? C + q : C + R + q;
           tasks[at] = make_uint2(slot, (uint32_t)T_SMALL << 28);
         } else {
-          const uint32_t f0 = s_base[b] + rank * 2 * nt, r0 = s_rowb[b] + rank * nb, i0 = s_colib[b] + rank * nt;
-#pragma nounroll
-          for (uint32_t t = 0; t < nt; t++) {
-            tasks[f0 + t] = make_uint2(slot, ((uint32_t)T_COLF_A << 28) | t);
-            tasks[f0 + nt + t] = make_uint2(slot, ((uint32_t)T_COLF_B << 28) | t);
-            tasks[i0 + t] = make_uint2(slot, ((uint32_t)T_COLI << 28) | t);
-          }
-#pragma nounroll
-          for (uint32_t j = 0; j < nb; j++) tasks[r0 + j] = make_uint2(slot, ((uint32_t)T_ROW << 28) | j);
+          // its tasks are written below, by the whole workgroup
+          s_eslot[ei] = slot;
+          s_ef0[ei] = s_base[b] + rank * 2 * nt;
+          s_ei0[ei] = s_colib[b] + rank * nt;
+          s_er0[ei] = s_rowb[b] + rank * nb;
+          s_ent[ei] = nt;
+          s_enb[ei] = nb;
         }
       }
       // one fix-up record per product: the top slot writes a split product's,
@@ -1650,6 +1654,19 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
       }
     }
     __syncthreads();
+    // The chunk's multi-pass tasks (3 ntiles + nblocks per slot): a wave
+    // per slot, its lanes on consecutive tasks, so every store of a wave
+    // covers 64 adjacent records.  (One lane per slot writing a 2^21
+    // product's 640 tasks took most of the planning time.)
+    for (uint32_t e = wave; e < (uint32_t)etot; e += kPlanWaves) {
+      const uint32_t sl = s_eslot[e], nt = s_ent[e], nb = s_enb[e];
+      const uint32_t f0 = s_ef0[e], i0 = s_ei0[e], r0 = s_er0[e];
+      for (uint32_t q = lane; q < 2 * nt; q += 64)
+        tasks[f0 + q] = make_uint2(sl, ((q < nt ? (uint32_t)T_COLF_A : (uint32_t)T_COLF_B) << 28) |
+                                           (q < nt ? q : q - nt));
+      for (uint32_t q = lane; q < nt; q += 64) tasks[i0 + q] = make_uint2(sl, ((uint32_t)T_COLI << 28) | q);
+      for (uint32_t q = lane; q < nb; q += 64) tasks[r0 + q] = make_uint2(sl, ((uint32_t)T_ROW << 28) | q);
+    }
     if (tid < (uint32_t)kPlanBuckets) {
       uint32_t add = 0;
       for (int w = 0; w < kPlanWaves; w++) add += s_wc[w][tid];
