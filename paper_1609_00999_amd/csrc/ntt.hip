@@ -1506,17 +1506,35 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   }
   __syncthreads();
   // Pass 1: validate, count slots per length, sum data words and chunks.
+  // Each wave sums its lanes first and makes one shared atomic per total
+  // (every lane adding to one shared word serialized thousands of atomics).
   for (uint32_t base = 0; base < nslots; base += kPlanThreads) {
     const uint32_t slot = base + tid;
+    uint32_t b = 0xFFu;
+    unsigned long long words = 0, chunks = 0;
     if (slot < nslots) {
       const int part = (int)(slot & 1u);
       const SlotShape sh = slot_shape(descs[slot >> 1], part, nprimes, s_logmax);
       if (sh.err) atomicCAS(&s_err, 0, sh.err);
       else if (sh.used) {
-        atomicAdd(&s_cnt[sh.n], 1u);
-        atomicAdd(&s_words, (unsigned long long)slot_words(sh, part));
-        atomicAdd(&s_chunks, (unsigned long long)slot_chunks(sh, part));
+        b = (uint32_t)sh.n;
+        words = slot_words(sh, part);
+        chunks = slot_chunks(sh, part);
       }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      words += __shfl_xor(words, d, 64);
+      chunks += __shfl_xor(chunks, d, 64);
+    }
+    if (lane == 0) {
+      atomicAdd(&s_words, words);
+      atomicAdd(&s_chunks, chunks);
+    }
+#pragma nounroll
+    for (uint32_t k = 0; k < (uint32_t)kPlanBuckets; k++) {
+      const uint64_t mask = __ballot(b == k);
+      if (lane == 0 && mask) atomicAdd(&s_cnt[k], (uint32_t)__popcll(mask));
     }
   }
   __syncthreads();
