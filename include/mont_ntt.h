@@ -242,7 +242,7 @@ MONT_API mont_status ntt_plan_destroy(ntt_plan* plan);
  * holds, inside d_scratch: the same split rule as ntt_plan_create and its
  * phase task order (forward column tiles, half the single tasks, row
  * blocks, the other half, inverse column tiles, each phase longest first,
- * products of one length in index order).  Then one persistent launch runs
+ * products of one length grouped by prime).  Then one persistent launch runs
  * every task and, for split products, one fix-up launch follows.  The call
  * performs no host-device copy and no allocation, so it can be captured in a
  * HIP graph, and every replay plans whatever descriptors d_descs then holds

@@ -1424,8 +1424,10 @@ __global__ void k_fill_zero(uint32_t* p, uint32_t n) {
 // slot by slot, the two length-N transforms of each multi-pass slot and the
 // output of each top part.  The task list is in phase order: forward column
 // tiles, the first half of the single-task slots, row blocks, the other
-// half, inverse column tiles, each phase longest transform first and slots
-// in index order within one length (the host planner's phase order).
+// half, inverse column tiles, each phase longest transform first and the
+// slots of one length prime by prime (the host planner's phase order; within
+// one prime and length, slots take their ranks in the order their lanes reach
+// a shared counter).
 // ---------------------------------------------------------------------------
 
 constexpr int kPlanThreads = 512;
@@ -1481,8 +1483,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   __shared__ int s_err;
   __shared__ uint32_t s_base[kPlanBuckets];         // first task of the length's slots in their phase
   __shared__ uint32_t s_rowb[kPlanBuckets], s_colib[kPlanBuckets];   // same, row blocks and inverse tiles
-  __shared__ uint32_t s_run[kPlanBuckets];          // slots of the length placed so far
-  __shared__ uint32_t s_wc[kPlanWaves][kPlanBuckets];
+  // per (length, prime): slots, then the first rank of the group within
+  // its length (primes in order), and the ranks handed out so far
+  __shared__ uint32_t s_bp[kPlanBuckets * 64], s_bpr[kPlanBuckets * 64];
   // the multi-pass slots of the current chunk of slots: slot, first forward
   // tile, first inverse tile and first row block task, tiles, blocks (their
   // tasks are written by the whole workgroup)
@@ -1495,9 +1498,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   const uint32_t lane = tid & 63u, wave = tid >> 6;
   const uint32_t nslots = 2 * count;
   for (uint32_t i = tid; i < 64; i += kPlanThreads) s_logmax[i] = i < nprimes ? primes[i].logmax : 0u;
-  if (tid < (uint32_t)kPlanBuckets) {
-    s_cnt[tid] = 0;
-    s_run[tid] = 0;
+  for (uint32_t i = tid; i < (uint32_t)kPlanBuckets * 64; i += kPlanThreads) {
+    s_bp[i] = 0;
+    s_bpr[i] = 0;
   }
   if (tid == 0) {
     s_words = 0;
@@ -1510,14 +1513,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   // (every lane adding to one shared word serialized thousands of atomics).
   for (uint32_t base = 0; base < nslots; base += kPlanThreads) {
     const uint32_t slot = base + tid;
-    uint32_t b = 0xFFu;
     unsigned long long words = 0, chunks = 0;
     if (slot < nslots) {
       const int part = (int)(slot & 1u);
-      const SlotShape sh = slot_shape(descs[slot >> 1], part, nprimes, s_logmax);
+      const polymul_desc d = descs[slot >> 1];
+      const SlotShape sh = slot_shape(d, part, nprimes, s_logmax);
       if (sh.err) atomicCAS(&s_err, 0, sh.err);
       else if (sh.used) {
-        b = (uint32_t)sh.n;
+        atomicAdd(&s_bp[sh.n * 64 + d.prime_id], 1u);
         words = slot_words(sh, part);
         chunks = slot_chunks(sh, part);
       }
@@ -1531,11 +1534,19 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
       atomicAdd(&s_words, words);
       atomicAdd(&s_chunks, chunks);
     }
-#pragma nounroll
-    for (uint32_t k = 0; k < (uint32_t)kPlanBuckets; k++) {
-      const uint64_t mask = __ballot(b == k);
-      if (lane == 0 && mask) atomicAdd(&s_cnt[k], (uint32_t)__popcll(mask));
+  }
+  __syncthreads();
+  // Slots per length, and each (length, prime) group's first rank: within
+  // a length the slots go prime by prime, so that tasks that run together
+  // read one prime's twiddle tables.
+  if (tid < (uint32_t)kPlanBuckets) {
+    uint32_t acc = 0;
+    for (uint32_t p = 0; p < 64; p++) {
+      const uint32_t c = s_bp[tid * 64 + p];
+      s_bp[tid * 64 + p] = acc;
+      acc += c;
     }
+    s_cnt[tid] = acc;
   }
   __syncthreads();
   const BatchLayout lay = batch_layout(count);
@@ -1589,7 +1600,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   FixDev* fixes = reinterpret_cast<FixDev*>(scr + lay.fixes);
   uint2* tasks = reinterpret_cast<uint2*>(scr + lay.tasks);
   const uint32_t C = s_C, R = s_R, half = s_half;
-  // Pass 2: ranks within each length (index order), data offsets and fix-up
+  // Pass 2: ranks within each length (by prime), data offsets and fix-up
   // chunks by prefix sums, then the records and the tasks.
   for (uint32_t base = 0; base < nslots; base += kPlanThreads) {
     const uint32_t slot = base + tid;
@@ -1598,23 +1609,16 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
     const polymul_desc d = slot < nslots ? descs[slot >> 1] : polymul_desc{};
     if (slot < nslots) sh = slot_shape(d, part, nprimes, s_logmax);
     const uint32_t b = sh.used ? (uint32_t)sh.n : 0xFFu;
-    uint32_t inwave = 0;
-#pragma nounroll
-    for (uint32_t k = 0; k < (uint32_t)kPlanBuckets; k++) {
-      const uint64_t mask = __ballot(b == k);
-      if (lane == 0) s_wc[wave][k] = (uint32_t)__popcll(mask);
-      if (b == k) inwave = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    }
     uint64_t wtot = 0, ctot = 0, etot = 0;
-    const uint64_t woff = plan_scan(slot_words(sh, part), s_wsum, &wtot);    // barriers also publish s_wc
+    const uint64_t woff = plan_scan(slot_words(sh, part), s_wsum, &wtot);
     const uint64_t coff = plan_scan(slot < nslots && part == 1 ? slot_chunks(sh, part) : 0u, s_wsum, &ctot);
     const uint32_t ei = (uint32_t)plan_scan(sh.used && sh.n > kRowLog ? 1u : 0u, s_wsum, &etot);
     if (slot < nslots) {
-      uint32_t rank = 0;
-      if (sh.used) {
-        rank = s_run[b] + inwave;
-        for (uint32_t w = 0; w < wave; w++) rank += s_wc[w][b];
-      }
+      // rank within the length: the (length, prime) group's first rank plus
+      // the order of arrival within the group (any order of the slots of one
+      // phase keeps every prerequisite ahead of its dependants, and the
+      // results do not depend on it)
+      const uint32_t rank = sh.used ? s_bp[b * 64 + d.prime_id] + atomicAdd(&s_bpr[b * 64 + d.prime_id], 1u) : 0u;
       const uint64_t dat = s_data + woff;
       const uint32_t chunk0 = (uint32_t)(s_chk + coff);
       if (sh.used) {
@@ -1684,11 +1688,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
                                            (q < nt ? q : q - nt));
       for (uint32_t q = lane; q < nt; q += 64) tasks[i0 + q] = make_uint2(sl, ((uint32_t)T_COLI << 28) | q);
       for (uint32_t q = lane; q < nb; q += 64) tasks[r0 + q] = make_uint2(sl, ((uint32_t)T_ROW << 28) | q);
-    }
-    if (tid < (uint32_t)kPlanBuckets) {
-      uint32_t add = 0;
-      for (int w = 0; w < kPlanWaves; w++) add += s_wc[w][tid];
-      s_run[tid] += add;
     }
     if (tid == 0) {
       s_data += wtot;
