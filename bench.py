@@ -647,8 +647,9 @@ def polymul_redc_count(da, db):
 
 def polymul_batch_extra(torch, wl, dev, leg=None):
     """2048 products, degrees log-uniform in [2^8, 2^20), 8 primes: one
-    persistent launch (eager and graph-replayed) against per-product plain
-    launches, all on the same inputs."""
+    persistent launch (eager, graph-replayed, and through the one-call entry
+    point planned on the device) against per-product plain launches, all on
+    the same inputs."""
     from paper_1609_00999_amd import ntt
     batch = wl.polymul_batch()
     ctx = ntt.Context(wl.PRIMES_NTT, 23)
@@ -684,6 +685,16 @@ def polymul_batch_extra(torch, wl, dev, leg=None):
     with torch.cuda.graph(g):
         plan.execute(din, dout, scr)
     t_graph = timed(torch, g.replay, 5, warmup=3)
+    # the same batch through the one-call entry point (descriptors in device
+    # memory, planned by the device), checked byte for byte against the plan
+    ref = dout.clone()
+    descs = ntt.make_descs(batch.prime_id, batch.da, batch.db, batch.a_off, batch.b_off, batch.c_off)
+    ddescs = ntt.descs_to_device(descs, dev)
+    oscr = torch.empty(ntt.batch_scratch_bytes(ctx, descs) // 4, dtype=torch.int32, device=dev)
+    oout = torch.empty_like(dout)
+    t_one = timed(torch, lambda: ntt.polymul_batch(ctx, ddescs, len(descs), din, oout, oscr), 5, warmup=3)
+    one_ok = ntt.batch_status(oscr) == 0 and bool(torch.equal(oout, ref))
+    del oscr, oout, ref
     # per-product plain launches
     big = max(ntt.scratch_bytes(int(a), int(b)) for a, b in zip(batch.da, batch.db))
     pscr = torch.empty(max(1, big // 4), dtype=torch.int32, device=dev)
@@ -700,6 +711,7 @@ def polymul_batch_extra(torch, wl, dev, leg=None):
     t_plain = timed(torch, plain, 2)
     res = {"products": batch.count, "status": st, "spot_check_failures": None if bad is None else int(bad),
            "persistent_ms": round(t_batch * 1e3, 3), "graph_ms": round(t_graph * 1e3, 3),
+           "one_call_ms": round(t_one * 1e3, 3), "one_call_equals_plan": one_ok,
            "plain_launches_ms": round(t_plain * 1e3, 3),
            "polymul_per_s": round(batch.count / t_batch, 1),
            "polymul_per_s_graph": round(batch.count / t_graph, 1),
