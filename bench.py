@@ -28,7 +28,7 @@ N_ELEM = 1 << 28
 # HBM bytes per mont_mul launch at n = 2^28 from two rocprofv3 --pmc runs
 # (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain
 # 1 GiB copy kernel gives), valid only for the kernel source they were taken on.
-MUL_TRAFFIC = {"src_hash": "8582760e327fdbc2", "n": 1 << 28, "bytes": 3145808 * 1024,
+MUL_TRAFFIC = {"src_hash": "86da17492fc5b1c5", "n": 1 << 28, "bytes": 3145800 * 1024,
                "profile": "profiles/elementwise_mul_muladd_n2e28_x4primes.md"}
 
 

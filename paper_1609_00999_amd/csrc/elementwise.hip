@@ -14,15 +14,24 @@ namespace mont {
 
 namespace {
 
-template <bool NT>
-__device__ __forceinline__ v4u ld(const v4u* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p);
-  else return *p;
+// The vector kernel addresses each workgroup tile through raw buffer
+// resources (CDNA buffer instructions): a resource in scalar registers holds
+// the tile's first address and its size in bytes, each lane one 32-bit
+// offset.  Loads past the size return 0 and stores past it are dropped (the
+// range check of raw, unstrided buffers), so the array's last, partial tile
+// needs no per-lane compare, and an address costs no 64-bit arithmetic.  NT:
+// the non-temporal cache policy (streamed data, read or written once).
+constexpr int kBufWord3 = 0x00020000;   // resource word 3 on gfx9: 32-bit data format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kBufWord3);
 }
 template <bool NT>
-__device__ __forceinline__ void st(v4u* p, v4u v) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p);
-  else *p = v;
+__device__ __forceinline__ v4u ld(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, NT ? 2 : 0);
+}
+template <bool NT>
+__device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t off, v4u v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, NT ? 2 : 0);
 }
 
 // x^e in the residue system by fixed 2-bit windows, most significant first.
@@ -100,7 +109,8 @@ constexpr int n_inputs() { return OP == OP_TO || OP == OP_FROM ? 1 : (OP == OP_M
 
 // Vector kernel: element i of every array is read once and the result
 // written once.  Workgroup w handles vectors [w*BLOCK*VPT, (w+1)*BLOCK*VPT),
-// lane l vector w*BLOCK*VPT + j*BLOCK + l for j < VPT (coalesced per j);
+// lane l vector w*BLOCK*VPT + j*BLOCK + l for j < VPT (coalesced per j),
+// through buffer resources sized to the tile's vectors inside the array;
 // the grid strides over workgroup tiles when nvec exceeds it.  The last
 // n - 4*nvec (< 4) elements are done by the first lanes of workgroup 0.
 template <int OP, int BLOCK, int VPT, bool NT>
@@ -111,26 +121,26 @@ __global__ __launch_bounds__(BLOCK) void k_elem_v4(Mod md, uint32_t kc, const ui
   constexpr int NIN = n_inputs<OP>();
   const size_t nvec = n >> 2;
   const size_t ntile = (nvec + (size_t)BLOCK * VPT - 1) / ((size_t)BLOCK * VPT);
-  const v4u* va = reinterpret_cast<const v4u*>(a);
-  const v4u* vb = reinterpret_cast<const v4u*>(b);
-  const v4u* vc = reinterpret_cast<const v4u*>(c);
-  v4u* vo = reinterpret_cast<v4u*>(out);
   for (size_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const size_t base = tile * ((size_t)BLOCK * VPT) + threadIdx.x;
+    const size_t first = tile * ((size_t)BLOCK * VPT);             // first vector of the tile
+    const size_t left = nvec - first;
+    const uint32_t bytes = (uint32_t)(left < (size_t)BLOCK * VPT ? left : (size_t)BLOCK * VPT) * 16u;
+    const __amdgpu_buffer_rsrc_t ra = tile_rsrc(a + 4 * first, bytes);
+    const __amdgpu_buffer_rsrc_t rb = tile_rsrc(NIN >= 2 ? b + 4 * first : a, bytes);
+    const __amdgpu_buffer_rsrc_t rc = tile_rsrc(NIN >= 3 ? c + 4 * first : a, bytes);
+    const __amdgpu_buffer_rsrc_t ro = tile_rsrc(out + 4 * first, bytes);
     v4u x[VPT], y[VPT], z[VPT];
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
-      const size_t i = base + (size_t)j * BLOCK;
-      if (i < nvec) {
-        x[j] = ld<NT>(va + i);
-        if constexpr (NIN >= 2) y[j] = ld<NT>(vb + i);
-        if constexpr (NIN >= 3) z[j] = ld<NT>(vc + i);
-      }
+      const uint32_t off = (threadIdx.x + (uint32_t)j * BLOCK) * 16u;
+      x[j] = ld<NT>(ra, off);
+      if constexpr (NIN >= 2) y[j] = ld<NT>(rb, off);
+      if constexpr (NIN >= 3) z[j] = ld<NT>(rc, off);
     }
 #pragma unroll
     for (int j = 0; j < VPT; j++) {
-      const size_t i = base + (size_t)j * BLOCK;
-      if (i < nvec) {
+      const uint32_t off = (threadIdx.x + (uint32_t)j * BLOCK) * 16u;
+      {
         v4u r;
         if constexpr (NIN == 1) {
           r.x = elem_op<OP>(x[j].x, 0, 0, md, kc);
@@ -148,7 +158,7 @@ __global__ __launch_bounds__(BLOCK) void k_elem_v4(Mod md, uint32_t kc, const ui
           r.z = elem_op<OP>(x[j].z, y[j].z, z[j].z, md, kc);
           r.w = elem_op<OP>(x[j].w, y[j].w, z[j].w, md, kc);
         }
-        st<NT>(vo + i, r);
+        st<NT>(ro, off, r);
       }
     }
   }
