@@ -10,6 +10,7 @@ namespace mont {
 namespace {
 
 typedef uint64_t v2u64 __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 
 struct Mod64 {
   uint64_t P;
@@ -69,6 +70,15 @@ __device__ __forceinline__ uint64_t apply64(uint64_t a, uint64_t b, uint64_t c, 
 
 constexpr int NIN(int op) { return op == OP64_MULADD ? 3 : (op == OP64_TO || op == OP64_FROM) ? 1 : 2; }
 
+// A workgroup's BLOCK vectors per pass are read and written through raw
+// buffer resources (their base address and size in scalar registers, a
+// 32-bit offset per lane, non-temporal policy; past the size loads return
+// zeros and stores are dropped), the form that streams fastest here.
+constexpr int kBufWord3 = 0x00020000;   // resource word 3 on gfx9: 32-bit data format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc64(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, kBufWord3);
+}
+
 // One 128-bit vector (two residues) per lane per pass, non-temporal, with a
 // scalar path for the ragged tail or for operands that are not 16-byte
 // aligned.
@@ -83,18 +93,21 @@ __global__ __launch_bounds__(BLOCK) void k_elem64(Mod64 md, uint64_t k, const ui
   size_t head = 0;
   if ((bits & 15u) == 0) {
     const size_t nvec = n >> 1;
-    const v2u64* va = reinterpret_cast<const v2u64*>(a);
-    const v2u64* vb = reinterpret_cast<const v2u64*>(b);
-    const v2u64* vc = reinterpret_cast<const v2u64*>(c);
-    v2u64* vo = reinterpret_cast<v2u64*>(out);
-    for (size_t i = tid; i < nvec; i += stride) {
-      const v2u64 x = __builtin_nontemporal_load(va + i);
+    const uint32_t off = threadIdx.x * 16u;
+    for (size_t first = (size_t)blockIdx.x * BLOCK; first < nvec; first += stride) {
+      const size_t left = nvec - first;
+      const uint32_t bytes = (uint32_t)(left < (size_t)BLOCK ? left : (size_t)BLOCK) * 16u;
+      const __amdgpu_buffer_rsrc_t ra = tile_rsrc64(a + 2 * first, bytes);
+      const __amdgpu_buffer_rsrc_t rb = tile_rsrc64(NIN(OP) >= 2 ? b + 2 * first : a, bytes);
+      const __amdgpu_buffer_rsrc_t rc = tile_rsrc64(NIN(OP) >= 3 ? c + 2 * first : a, bytes);
+      const __amdgpu_buffer_rsrc_t ro = tile_rsrc64(out + 2 * first, bytes);
+      const v2u64 x = __builtin_bit_cast(v2u64, __builtin_amdgcn_raw_buffer_load_b128(ra, (int)off, 0, 2));
       v2u64 y = x, z = x, r;
-      if constexpr (NIN(OP) >= 2) y = __builtin_nontemporal_load(vb + i);
-      if constexpr (NIN(OP) >= 3) z = __builtin_nontemporal_load(vc + i);
+      if constexpr (NIN(OP) >= 2) y = __builtin_bit_cast(v2u64, __builtin_amdgcn_raw_buffer_load_b128(rb, (int)off, 0, 2));
+      if constexpr (NIN(OP) >= 3) z = __builtin_bit_cast(v2u64, __builtin_amdgcn_raw_buffer_load_b128(rc, (int)off, 0, 2));
       r.x = apply64<OP>(x.x, y.x, z.x, md, k);
       r.y = apply64<OP>(x.y, y.y, z.y, md, k);
-      __builtin_nontemporal_store(r, vo + i);
+      __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u32, r), ro, (int)off, 0, 2);
     }
     head = nvec << 1;
   }
