@@ -1343,16 +1343,22 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
 // A batch planned on the device passes dyn_nchunks, its header word holding
 // the chunk count (its records of unsplit products have m = 0 and are never
 // selected: each shares its first chunk index with a later record).
+// A plan made once on the host passes owner, the record of every chunk, so a
+// chunk's loads wait on two dependent reads instead of the search's dozen.
 __global__ __launch_bounds__(256) void k_split_fix(const PrimeDev* primes, const FixDev* fx, uint32_t nfix,
                                                    uint32_t nchunks, uint32_t* out, const uint32_t* scr,
-                                                   const uint32_t* dyn_nchunks) {
+                                                   const uint32_t* dyn_nchunks, const uint32_t* owner) {
   if (dyn_nchunks) nchunks = *dyn_nchunks;
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
     uint32_t lo = 0, hi = nfix;                  // fx[lo].chunk0 <= c < fx[hi].chunk0
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (fx[mid].chunk0 <= c) lo = mid;
-      else hi = mid;
+    if (owner) {
+      lo = owner[c];
+    } else {
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (fx[mid].chunk0 <= c) lo = mid;
+        else hi = mid;
+      }
     }
     const FixDev d = fx[lo];
     uint32_t* cc = out + d.c_off;
@@ -1851,6 +1857,7 @@ struct ntt_plan {
   uint32_t nchunks = 0;     // fix-up chunks
   uint64_t redc = 0;        // REDC one execution performs
   FixDev* d_fix = nullptr;
+  uint32_t* d_owner = nullptr;  // plans made once: the fix-up record of each chunk
   int default_grid = 0;
   // Reusable plans (ntt_plan_reserve): one device block and one pinned
   // staging block of the same capacity.  An update packs its products, fix-ups
@@ -2481,6 +2488,7 @@ void free_plan(ntt_plan* plan) {
     (void)hipFree(plan->d_prods);
     (void)hipFree(plan->d_tasks);
     (void)hipFree(plan->d_fix);
+    (void)hipFree(plan->d_owner);
   }
   if (plan->staged) (void)hipEventDestroy(plan->staged);
   delete plan;
@@ -2518,10 +2526,16 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
   plan->scratch_words = scr;
   plan->in_words = in_words;
   plan->out_words = out_words;
+  std::vector<uint32_t> owner(nchunks);
+  for (size_t i = 0; i < fixes.size(); i++) {
+    const uint32_t c1 = fixes[i].chunk0 + (fixes[i].m + kFixChunk - 1) / kFixChunk;
+    for (uint32_t c = fixes[i].chunk0; c < c1; c++) owner[c] = (uint32_t)i;
+  }
   if (!prods.empty()) {
     if (hipMalloc(&plan->d_prods, sizeof(ProdDev) * prods.size()) != hipSuccess ||
         hipMalloc(&plan->d_tasks, sizeof(uint2) * std::max<size_t>(1, tasks.size())) != hipSuccess ||
-        (!fixes.empty() && hipMalloc(&plan->d_fix, sizeof(FixDev) * fixes.size()) != hipSuccess)) {
+        (!fixes.empty() && hipMalloc(&plan->d_fix, sizeof(FixDev) * fixes.size()) != hipSuccess) ||
+        (nchunks && hipMalloc(&plan->d_owner, sizeof(uint32_t) * nchunks) != hipSuccess)) {
       free_plan(plan);
       return MONT_ENOMEM;
     }
@@ -2529,7 +2543,9 @@ extern "C" mont_status ntt_plan_create(const ntt_ctx* ctx, const polymul_desc* d
         (tasks.size() && hipMemcpy(plan->d_tasks, tasks.data(), sizeof(uint2) * tasks.size(),
                                    hipMemcpyHostToDevice) != hipSuccess) ||
         (fixes.size() && hipMemcpy(plan->d_fix, fixes.data(), sizeof(FixDev) * fixes.size(),
-                                   hipMemcpyHostToDevice) != hipSuccess)) {
+                                   hipMemcpyHostToDevice) != hipSuccess) ||
+        (nchunks && hipMemcpy(plan->d_owner, owner.data(), sizeof(uint32_t) * nchunks, hipMemcpyHostToDevice) !=
+                        hipSuccess)) {
       free_plan(plan);
       return MONT_EHIP;
     }
@@ -2710,9 +2726,11 @@ extern "C" mont_status ntt_plan_execute(const ntt_plan* plan, const uint32_t* d_
   gsz = std::max(1u, std::min(gsz, plan->ntasks));
   launch_persistent(g, gsz, s, plan->shape);
   if (plan->nfix > 0)
-    // one workgroup per chunk: the chunks' record searches run in parallel
+    // one workgroup per chunk; a reusable plan has no owner table and each
+    // chunk searches the records
     hipLaunchKernelGGL(k_split_fix, dim3(plan->nchunks), dim3(256), 0, s, plan->ctx->d_primes,
-                       plan->d_fix, plan->nfix, plan->nchunks, d_out, static_cast<const uint32_t*>(scr), nullptr);
+                       plan->d_fix, plan->nfix, plan->nchunks, d_out, static_cast<const uint32_t*>(scr), nullptr,
+                       plan->d_owner);
   return last_launch_status();
 }
 
@@ -2789,7 +2807,7 @@ extern "C" mont_status ntt_polymul_batch(const ntt_ctx* ctx, const polymul_desc*
   // chunks of most batches at one workgroup each, striding beyond
   hipLaunchKernelGGL(k_split_fix, dim3(32768), dim3(256), 0, s, ctx->d_primes,
                      reinterpret_cast<const FixDev*>(scr + lay.fixes), (uint32_t)count, 0u, d_out,
-                     static_cast<const uint32_t*>(scr), scr + kHdrNchunks);
+                     static_cast<const uint32_t*>(scr), scr + kHdrNchunks, nullptr);
   return last_launch_status();
 }
 
