@@ -251,8 +251,9 @@ MONT_API mont_status ntt_plan_destroy(ntt_plan* plan);
  * ntt_scratch_bytes -- bytes of d_scratch that ntt_polymul_batch needs for
  * these `count` descriptors (a HOST array here, with the values the device
  * copy will hold): a header, per-product records and counters, the task
- * list, 2N words for each product of N > 2^13 after splitting, and the
- * outputs of top parts.  Returns 0 if ctx is NULL or a descriptor is invalid
+ * list, 2N words for each product of N > 2^13 after splitting, the
+ * outputs of top parts, and one word per 1024 coefficients that a two-part
+ * product's fix-up rewrites.  Returns 0 if ctx is NULL or a descriptor is invalid
  * (prime_id out of range, reserved != 0, da+db+1 > 2^31, N above the prime's
  * table).  Pure host arithmetic, for admission by footprint.
  *

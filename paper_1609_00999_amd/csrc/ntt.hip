@@ -111,8 +111,9 @@ constexpr int kHdrWords = 64;          // [0] queue head, [1] status
 constexpr uint32_t kStatusTimeout = 1;
 // A batch planned on the device (ntt_polymul_batch) also keeps in its header
 // the task count, the fix-up chunk count, a planning error (a negative
-// mont_status, 0 if none) and the scratch words the plan needs (64-bit).
-constexpr int kHdrNtasks = 2, kHdrNchunks = 3, kHdrError = 4, kHdrWordsNeeded = 6;
+// mont_status, 0 if none), the scratch words the plan needs (64-bit) and the
+// word offset of the table of each fix-up chunk's record (64-bit).
+constexpr int kHdrNtasks = 2, kHdrNchunks = 3, kHdrError = 4, kHdrWordsNeeded = 6, kHdrOwner = 8;
 constexpr uint32_t kStatusPlanError = 2;
 
 // ---------------------------------------------------------------------------
@@ -1340,15 +1341,19 @@ __global__ __launch_bounds__(NT, NT >= 1024 ? 4 : NT / 128) void k_ntt_persisten
 // device (a workgroup takes chunks; the fix-up of a chunk is found by binary
 // search on the chunks' first indices).  The cyclic part left c[k] = c_k +
 // c_(h+k); the top product t gives c_(h+k) = t[m-1+k].
-// A batch planned on the device passes dyn_nchunks, its header word holding
-// the chunk count (its records of unsplit products have m = 0 and are never
-// selected: each shares its first chunk index with a later record).
-// A plan made once on the host passes owner, the record of every chunk, so a
-// chunk's loads wait on two dependent reads instead of the search's dozen.
+// owner, when given, holds the record of every chunk, so a chunk's loads
+// wait on two dependent reads instead of the search's dozen.  A plan made
+// once on the host passes its own table; a batch planned on the device
+// passes dyn (its scratch header, which holds the chunk count and where the
+// planner put the table; its records of unsplit products have m = 0 and own
+// no chunk).
 __global__ __launch_bounds__(256) void k_split_fix(const PrimeDev* primes, const FixDev* fx, uint32_t nfix,
                                                    uint32_t nchunks, uint32_t* out, const uint32_t* scr,
-                                                   const uint32_t* dyn_nchunks, const uint32_t* owner) {
-  if (dyn_nchunks) nchunks = *dyn_nchunks;
+                                                   const uint32_t* dyn, const uint32_t* owner) {
+  if (dyn) {
+    nchunks = dyn[kHdrNchunks];
+    owner = dyn + ((uint64_t)dyn[kHdrOwner] | ((uint64_t)dyn[kHdrOwner + 1] << 32));
+  }
   for (uint32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
     uint32_t lo = 0, hi = nfix;                  // fx[lo].chunk0 <= c < fx[hi].chunk0
     if (owner) {
@@ -1426,9 +1431,10 @@ __global__ void k_fill_zero(uint32_t* p, uint32_t n) {
 // captured graph replays with whatever descriptors the buffer then holds.
 //
 // Scratch layout (words): header | 2 counters x 2 count slots | ProdDev x 2
-// count | FixDev x count | tasks | data (64-word aligned), where data holds,
-// slot by slot, the two length-N transforms of each multi-pass slot and the
-// output of each top part.  The task list is in phase order: forward column
+// count | FixDev x count | tasks | data (64-word aligned) | chunk table,
+// where data holds, slot by slot, the two length-N transforms of each
+// multi-pass slot and the output of each top part, and the chunk table the
+// record of each fix-up chunk.  The task list is in phase order: forward column
 // tiles, the first half of the single-task slots, row blocks, the other
 // half, inverse column tiles, each phase longest transform first and the
 // slots of one length prime by prime (the host planner's phase order; within
@@ -1497,9 +1503,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   // tasks are written by the whole workgroup)
   __shared__ uint32_t s_eslot[kPlanThreads], s_ef0[kPlanThreads], s_ei0[kPlanThreads], s_er0[kPlanThreads];
   __shared__ uint32_t s_ent[kPlanThreads], s_enb[kPlanThreads];
+  // the split products of the current chunk of slots: first fix-up chunk,
+  // chunks, record (their entries of the chunk table)
+  __shared__ uint32_t s_fc0[kPlanThreads], s_fcn[kPlanThreads], s_fid[kPlanThreads];
   __shared__ uint64_t s_wsum[kPlanWaves];
   __shared__ uint32_t s_C, s_R, s_half;
-  __shared__ uint64_t s_data, s_chk;
+  __shared__ uint64_t s_data, s_chk, s_own;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u, wave = tid >> 6;
   const uint32_t nslots = 2 * count;
@@ -1584,7 +1593,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
     s_R = R;
     s_half = half;
     const uint64_t ntasks = (uint64_t)C + S + R + I;
-    const uint64_t need = batch_data_offset(lay, ntasks) + s_words;
+    // the chunk table follows the data
+    const uint64_t own = batch_data_offset(lay, ntasks) + s_words;
+    const uint64_t need = own + s_chunks;
     int err = s_err;
     if (!err && need > scr_words) err = MONT_ENOMEM;
     if (!err && ntasks > 0xFFFFFFFFull) err = MONT_ERANGE;
@@ -1596,8 +1607,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
     scr[kHdrError] = (uint32_t)err;
     scr[kHdrWordsNeeded] = (uint32_t)need;
     scr[kHdrWordsNeeded + 1] = (uint32_t)(need >> 32);
+    scr[kHdrOwner] = (uint32_t)own;
+    scr[kHdrOwner + 1] = (uint32_t)(own >> 32);
     s_data = batch_data_offset(lay, ntasks);
     s_chk = 0;
+    s_own = own;
   }
   __syncthreads();
   if (s_err) return;                                 // uniform: every thread leaves
@@ -1605,6 +1619,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
   ProdDev* prods = reinterpret_cast<ProdDev*>(scr + lay.prods);
   FixDev* fixes = reinterpret_cast<FixDev*>(scr + lay.fixes);
   uint2* tasks = reinterpret_cast<uint2*>(scr + lay.tasks);
+  uint32_t* owner = scr + s_own;
   const uint32_t C = s_C, R = s_R, half = s_half;
   // Pass 2: ranks within each length (by prime), data offsets and fix-up
   // chunks by prefix sums, then the records and the tasks.
@@ -1615,10 +1630,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
     const polymul_desc d = slot < nslots ? descs[slot >> 1] : polymul_desc{};
     if (slot < nslots) sh = slot_shape(d, part, nprimes, s_logmax);
     const uint32_t b = sh.used ? (uint32_t)sh.n : 0xFFu;
-    uint64_t wtot = 0, ctot = 0, etot = 0;
+    uint64_t wtot = 0, ctot = 0, etot = 0, ftot = 0;
     const uint64_t woff = plan_scan(slot_words(sh, part), s_wsum, &wtot);
     const uint64_t coff = plan_scan(slot < nslots && part == 1 ? slot_chunks(sh, part) : 0u, s_wsum, &ctot);
     const uint32_t ei = (uint32_t)plan_scan(sh.used && sh.n > kRowLog ? 1u : 0u, s_wsum, &etot);
+    const uint32_t fi = (uint32_t)plan_scan(sh.split && part == 1 ? 1u : 0u, s_wsum, &ftot);
     if (slot < nslots) {
       // rank within the length: the (length, prime) group's first rank plus
       // the order of arrival within the group (any order of the slots of one
@@ -1675,6 +1691,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
         f.prime_id = d.prime_id;
         f.s_log = (uint32_t)sh.n;
         fixes[slot >> 1] = f;
+        s_fc0[fi] = chunk0;
+        s_fcn[fi] = slot_chunks(sh, part);
+        s_fid[fi] = slot >> 1;
       } else if (!sh.split && part == 0) {
         FixDev f = {};
         f.chunk0 = chunk0;
@@ -1694,6 +1713,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const PrimeDev* pri
                                            (q < nt ? q : q - nt));
       for (uint32_t q = lane; q < nt; q += 64) tasks[i0 + q] = make_uint2(sl, ((uint32_t)T_COLI << 28) | q);
       for (uint32_t q = lane; q < nb; q += 64) tasks[r0 + q] = make_uint2(sl, ((uint32_t)T_ROW << 28) | q);
+    }
+    for (uint32_t e = wave; e < (uint32_t)ftot; e += kPlanWaves) {
+      const uint32_t c0 = s_fc0[e], nc = s_fcn[e], id = s_fid[e];
+      for (uint32_t q = lane; q < nc; q += 64) owner[c0 + q] = id;
     }
     if (tid == 0) {
       s_data += wtot;
@@ -2765,7 +2788,7 @@ extern "C" mont_status ntt_plan_status_async(const ntt_plan* plan, const void* d
 extern "C" size_t ntt_scratch_bytes(const ntt_ctx* ctx, const polymul_desc* descs, int count) {
   if (!ctx || count < 0 || (count > 0 && !descs)) return 0;
   const uint32_t np = (uint32_t)ctx->params.size();
-  uint64_t ntasks = 0, words = 0;
+  uint64_t ntasks = 0, words = 0, chunks = 0;
   for (int i = 0; i < count; i++)
     for (int part = 0; part < 2; part++) {
       const SlotShape sh = slot_shape(descs[i], part, np, ctx->logmax.data());
@@ -2773,8 +2796,10 @@ extern "C" size_t ntt_scratch_bytes(const ntt_ctx* ctx, const polymul_desc* desc
       if (!sh.used) continue;
       ntasks += product_tasks(sh.n);
       words += slot_words(sh, part);
+      chunks += slot_chunks(sh, part);
     }
-  return (size_t)(batch_data_offset(batch_layout((uint32_t)count), ntasks) + words) * 4;
+  // header, records and tasks | data | the fix-up chunks' record table
+  return (size_t)(batch_data_offset(batch_layout((uint32_t)count), ntasks) + words + chunks) * 4;
 }
 
 extern "C" mont_status ntt_polymul_batch(const ntt_ctx* ctx, const polymul_desc* d_descs, int count,
@@ -2807,7 +2832,7 @@ extern "C" mont_status ntt_polymul_batch(const ntt_ctx* ctx, const polymul_desc*
   // chunks of most batches at one workgroup each, striding beyond
   hipLaunchKernelGGL(k_split_fix, dim3(32768), dim3(256), 0, s, ctx->d_primes,
                      reinterpret_cast<const FixDev*>(scr + lay.fixes), (uint32_t)count, 0u, d_out,
-                     static_cast<const uint32_t*>(scr), scr + kHdrNchunks, nullptr);
+                     static_cast<const uint32_t*>(scr), scr, nullptr);
   return last_launch_status();
 }
 
