@@ -66,6 +66,35 @@ def test_vector_batch_uneven(mods):
     b.close()
 
 
+def test_vector_batch_uploaded_uneven_and_misaligned(mods):
+    """Above 16 vectors the descriptors are uploaded and a workgroup takes two
+    adjacent tiles: pairs that straddle two vectors, partial last tiles,
+    empty vectors, vectors not 16-byte aligned (offsets of 1-3 words) and an
+    odd tile count, against the oracle."""
+    mont = mods[0]
+    rng = np.random.default_rng(11)
+    base = [0, 1, 3, 4095, 4096, 4097, 8192, 10000, 123457, 1 << 20, 5, 0, 70000, 12288, 3 * 4096 + 1, 2]
+    sizes = base + base[::-1] + [4096]
+    assert sum((n + 4095) // 4096 for n in sizes) % 2 == 1
+    b = mont.Batch(len(sizes))
+    items, refs = [], []
+    for i, n in enumerate(sizes):
+        P = (list(wl.PRIMES_BW) + list(PRIMES))[i % 12]
+        prm = mont.setup(P)
+        a = rng.integers(0, P, n + 3, dtype=np.uint32)
+        c = rng.integers(0, P, n + 3, dtype=np.uint32)
+        off = (i * 3) % 4
+        da, dc = dev(a)[off:off + n], dev(c)[off:off + n]
+        out = torch.empty(n + 3, dtype=torch.int32, device="cuda")[off:off + n]
+        items.append((prm, da, dc, out))
+        refs.append(oracle.mont_mul(P, a[off:off + n], c[off:off + n]))
+    b.update(items)
+    b.mul()
+    for i, ((_, _, _, out), ref) in enumerate(zip(items, refs)):
+        assert np.array_equal(host(out), ref), (i, sizes[i])
+    b.close()
+
+
 def test_vector_batch_large_and_small_in_turn(mods):
     """Batches above 16 vectors upload their descriptors; smaller ones pass
     them in the launch.  One object alternates between the two."""
